@@ -1,0 +1,199 @@
+/*
+ * cubics.h - C ABI of the MI355X (gfx950) CSP solver library libcubics.so.
+ *
+ * The library solves constraint satisfaction problems P = (X, D, C) as the
+ * paper states them (Sec. 1.1, "Constraint programming"): X is a set of
+ * integer variables, D their finite domains and C a set of constraints, each
+ * a subset of the cartesian product of its variables' domains.  A solution
+ * assigns every variable a value of its domain so that every constraint
+ * holds.  Solving interleaves the three operations of Sec. 1.1 - labeling,
+ * constraint propagation and backtracking - and, as Sec. 2.1 prescribes, runs
+ * all of them on the GPU after one upload: bitset domains are revised to a
+ * fixpoint, and many depth-first subtrees are searched at once by a
+ * persistent kernel with per-worker trail stacks and a global work queue.
+ *
+ * Conventions (all calls):
+ *  - Return value 0 (CUBICS_OK) or a negative error code.  On error no handle
+ *    is returned, nothing leaks, and cubics_last_error() gives a message
+ *    (thread-local, valid until the next call on the same thread).
+ *  - Host pointers are read during the call only and copied; the caller may
+ *    free them on return.  Device pointers (marked "device") are written on
+ *    the context's stream and stay owned by the caller.
+ *  - Every call that runs GPU work is synchronous with respect to the host:
+ *    it returns after the work finished on the context's stream.
+ *  - One context per host thread; contexts are not thread-safe.
+ */
+#ifndef CUBICS_H
+#define CUBICS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ error codes */
+#define CUBICS_OK 0
+#define CUBICS_EINVAL (-1)       /* malformed argument or instance */
+#define CUBICS_ENOMEM (-2)       /* host or device allocation failed */
+#define CUBICS_EDEVICE (-3)      /* a HIP call failed */
+#define CUBICS_EUNSUPPORTED (-4) /* valid CSP outside the supported range */
+
+/* ------------------------------------------------------- constraint types
+ * The flat constraint list given to cubics_load (same layout as the
+ * extensional form of Sec. 1.1: a constraint is its scope plus the set of
+ * allowed tuples, given either explicitly or by a closed rule).
+ *   UNARY      scope (i)    table: ceil(d_i/32) words, bit a <=> value lo_i+a allowed
+ *   TABLE2     scope (i,j)  table: d_i rows of ceil(d_j/32) words; bit b of row a
+ *                           set <=> the pair (lo_i+a, lo_j+b) is allowed
+ *   NEQ        scope (i,j)  params {off}: x_i != x_j + off
+ *   LT         scope (i,j)  params {off}: x_i <  x_j + off
+ *   QUEENS     scope (i,j)  params {k}:   x_i != x_j and |x_i - x_j| != k
+ *   ALLDIFF    scope (v_0..v_{k-1}), all with the same lo: pairwise distinct
+ *   LINEAR_LE  scope (v_0..v_{k-1}); params {b, a_0..a_{k-1}}, every a_t > 0:
+ *                           sum_t a_t x_{v_t} <= b
+ */
+enum {
+    CUBICS_UNARY = 0,
+    CUBICS_TABLE2 = 1,
+    CUBICS_NEQ = 2,
+    CUBICS_LT = 3,
+    CUBICS_QUEENS = 4,
+    CUBICS_ALLDIFF = 5,
+    CUBICS_LINEAR_LE = 6
+};
+
+/* solve modes */
+enum { CUBICS_MODE_FIRST = 0, CUBICS_MODE_ALL = 1, CUBICS_MODE_COUNT = 2 };
+/* verdicts */
+enum { CUBICS_SAT = 0, CUBICS_UNSAT = 1, CUBICS_LIMIT = 2, CUBICS_CANCELLED = 3 };
+/* branching heuristics */
+enum { CUBICS_BRANCH_FIRST_FAIL = 0, CUBICS_BRANCH_LEARNED = 1 };
+/* revision layouts for binary constraints (see cubics_solve) */
+enum { CUBICS_LAYOUT_AUTO = 0, CUBICS_LAYOUT_LANE = 1, CUBICS_LAYOUT_SEG = 2 };
+
+/* Supported range: 1 <= d_i <= 256 values per variable (at most 8 32-bit
+   words per domain); n <= 1024 variables with n * ceil(dmax/32) <= 4096;
+   at most 65535 global (ALLDIFF / LINEAR_LE) constraints per instance. */
+#define CUBICS_MAX_DOMAIN 256
+#define CUBICS_MAX_VARS 1024
+
+typedef struct cubics_ctx cubics_ctx;
+typedef struct cubics_prob cubics_prob;
+typedef struct cubics_policy cubics_policy;
+
+typedef struct {
+    uint64_t max_nodes;      /* per instance; 0 = unlimited.  Reaching it gives LIMIT */
+    uint64_t max_solutions;  /* per instance count cap; 0 = none.  Reaching it gives LIMIT
+                                with count == max_solutions */
+    int64_t time_ms;         /* wall budget of the search kernel; 0 = none */
+    int32_t branching;       /* CUBICS_BRANCH_* */
+    int32_t layout;          /* CUBICS_LAYOUT_*; AUTO uses the autotuned choice */
+    int64_t split_target;    /* eager subtree splitting until this many subproblems were
+                                queued; 0 = no eager split (work is shared by donation) */
+    int32_t *sol_buf;        /* device, caller-owned: sol_capacity x n int32 values, or NULL */
+    uint64_t sol_capacity;   /* solutions that fit in sol_buf */
+    int32_t workers;         /* persistent workers (wavefronts); 0 = fill the device */
+    int32_t donate;          /* 1 = busy workers donate subtrees to idle ones (default) */
+    const cubics_policy *policy; /* required when branching == LEARNED */
+} cubics_limits;
+
+typedef struct {
+    int32_t verdict;     /* CUBICS_SAT / UNSAT / LIMIT / CANCELLED */
+    int32_t truncated;   /* 1 if more solutions were found than fit in sol_buf */
+    uint64_t count;      /* solutions found (exact unless LIMIT/CANCELLED; then a lower
+                            bound, and min(found, max_solutions) under a cap) */
+    uint64_t n_written;  /* solutions stored in sol_buf */
+    uint64_t nodes;      /* search nodes: the root and every child tried */
+    uint64_t fails;      /* nodes whose propagation failed */
+    uint64_t revisions;  /* constraint revisions executed (schedule dependent) */
+    uint64_t steals;     /* subtrees donated between workers */
+    uint64_t alg_bytes;  /* algorithmic domain/table/trail bytes of the revisions and
+                            trail operations executed */
+    uint64_t tasks;      /* work-queue tasks processed */
+    double ms;           /* host wall time of the call */
+    double kernel_ms;    /* duration of the search kernel (HIP events on the stream) */
+} cubics_result;
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *cubics_last_error(void);
+
+/* --------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+   (a hipStream_t; NULL = the null stream).  The context owns scratch device
+   memory (work queue, trail stacks) that grows on demand. */
+int cubics_create(int32_t device, void *hip_stream, cubics_ctx **out);
+void cubics_destroy(cubics_ctx *ctx);
+int cubics_set_stream(cubics_ctx *ctx, void *hip_stream);
+/* Ask a running solve on this context to stop (safe from another thread);
+   the solve then returns verdict CANCELLED.  cubics_solve clears the flag on entry. */
+void cubics_cancel(cubics_ctx *ctx);
+
+/* ------------------------------------------------------------------ load */
+
+/* Pack one CSP (Sec. 2.1: the host builds the data structures and moves
+   them to GPU memory once).  Arrays (host):
+     lo[n], dsize[n]                 value range of each variable
+     init_bits[n * W] or NULL        W = ceil(max dsize / 32); optional initial domains
+                                     (bit a of row i = value lo_i + a); an empty initial
+                                     domain is not an error (the solve returns UNSAT)
+     type[m], arity[m]               CUBICS_* type and scope size of each constraint
+     var_off[m+1], vars[]            scope of constraint c = vars[var_off[c] .. var_off[c+1])
+     par_off[m+1], params[]          integer parameters (see the type list)
+     tab_off[m+1], tabs[]            packed bit rows (UNARY, TABLE2), in uint32 words
+   Errors: EINVAL for a variable index out of range, a wrong arity, repeated
+   scope variables, dsize < 1, a table of the wrong length, a non-positive
+   linear coefficient; EUNSUPPORTED for dsize > 256, n > 1024, an ALLDIFF
+   over variables with different lo, or a linear sum that may overflow int64.
+   n == 0 is valid (one empty solution). */
+int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const int32_t *dsize,
+                const uint32_t *init_bits, int32_t m, const int32_t *type,
+                const int32_t *arity, const int64_t *var_off, const int32_t *vars,
+                const int64_t *par_off, const int64_t *params, const int64_t *tab_off,
+                const uint32_t *tabs, cubics_prob **out);
+void cubics_free(cubics_prob *prob);
+/* n, W (words per domain) and the number of propagators of a loaded problem. */
+int cubics_prob_info(const cubics_prob *prob, int32_t *n, int32_t *W, int32_t *n_units,
+                     int32_t *n_global);
+
+/* ------------------------------------------------------------- propagate */
+
+/* Root propagation only (Sec. 1.1 "constraint propagation"): the initial
+   domains restricted by UNARY constraints, revised on the GPU to the fixpoint
+   of all constraints.  out_bits (host, n * W words) receives the fixpoint
+   domains; *failed = 1 if a domain emptied or a constraint test failed. */
+int cubics_root(cubics_prob *prob, int32_t layout, uint32_t *out_bits, int32_t *failed);
+
+/* ----------------------------------------------------------------- solve */
+
+/* Search one problem (Sec. 1.1 labeling + propagation + backtracking, Sec. 2.2
+   parallel propagation and per-domain save/restore), entirely on the GPU.
+   mode FIRST: stop at the first solution and store it in sol_buf[0..n);
+   ALL: count every solution and store up to sol_capacity of them (unordered);
+   COUNT: count only (sol_buf may still receive up to sol_capacity).
+   Branching: first-fail (fewest values, lowest index on ties), values in
+   ascending order; LEARNED picks the variable by the policy network instead,
+   which changes the order of the search but never its result.
+   Hitting max_nodes / max_solutions / time_ms is a verdict (LIMIT), not an
+   error.  `limits` may be NULL (no limits, defaults). */
+int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits,
+                 cubics_result *result);
+
+/* Solve B problems in one persistent launch (work-queue tasks are tagged by
+   instance).  limits[b] gives the per-instance max_nodes, max_solutions,
+   sol_buf and sol_capacity; the launch-wide knobs (time_ms, branching,
+   layout, split_target, workers, donate, policy) come from limits[0].
+   results[b] receives each instance's verdict and counters; kernel_ms and ms
+   are those of the whole launch.  All problems must come from contexts on the
+   same device; the work runs on the first problem's context stream. */
+int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
+                       const cubics_limits *limits, cubics_result *results);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CUBICS_H */

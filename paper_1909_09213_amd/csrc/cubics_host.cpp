@@ -1,0 +1,720 @@
+// Host side of libcubics: argument validation, packing of a CSP into the
+// device layout (Sec. 2.1: the CPU builds the data structures and moves them
+// to GPU memory once), solve orchestration and result readback.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/cubics.h"
+#include "cubics_internal.h"
+
+namespace cubics {
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st);
+hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
+                       unsigned long long *revs, size_t lds, hipStream_t st);
+hipError_t launch_init(const SearchParams &P, hipStream_t st);
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds);
+}  // namespace cubics
+
+using namespace cubics;
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(CUBICS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *cubics_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------- device buffers
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    int ensure(size_t bytes) {
+        if (bytes <= cap) return 0;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = std::max<size_t>(bytes, 256);
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            return fail(CUBICS_ENOMEM, "hipMalloc(%zu) failed", want);
+        }
+        cap = want;
+        return 0;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct cubics_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int cu_count = 0;
+    int wall_khz = 100000;
+    DevBuf inst, ctl, q, qseq, qdata, trail, rootout;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
+    std::map<std::string, int> tuned;  // shape bucket -> layout
+};
+
+struct cubics_prob {
+    cubics_ctx *ctx = nullptr;
+    void *blob = nullptr;
+    InstDev dev;  // with device pointers into blob
+    int n = 0, W = 1, dmax = 1;
+    int n_units = 0, n_glob = 0;
+    bool has_table = false;
+    std::string bucket;
+};
+
+// ----------------------------------------------------------------- context
+extern "C" int cubics_create(int32_t device, void *hip_stream, cubics_ctx **out) {
+    if (!out) return fail(CUBICS_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(CUBICS_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    cubics_ctx *c = new cubics_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return fail(CUBICS_EDEVICE, "hipGetDeviceProperties failed");
+    }
+    c->cu_count = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipHostMalloc((void **)&c->cancel_host, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        cubics_destroy(c);
+        return fail(CUBICS_EDEVICE, "event / pinned flag allocation failed");
+    }
+    *c->cancel_host = 0;
+    *out = c;
+    return CUBICS_OK;
+}
+
+extern "C" void cubics_destroy(cubics_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    c->inst.release(); c->ctl.release(); c->q.release(); c->qseq.release();
+    c->qdata.release(); c->trail.release(); c->rootout.release();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->cancel_host) (void)hipHostFree(c->cancel_host);
+    delete c;
+}
+
+extern "C" int cubics_set_stream(cubics_ctx *c, void *hip_stream) {
+    if (!c) return fail(CUBICS_EINVAL, "ctx is NULL");
+    c->stream = (hipStream_t)hip_stream;
+    return CUBICS_OK;
+}
+
+extern "C" void cubics_cancel(cubics_ctx *c) {
+    if (c && c->cancel_host) __atomic_store_n(c->cancel_host, 1, __ATOMIC_RELEASE);
+}
+
+// -------------------------------------------------------------------- load
+namespace {
+
+struct Packer {
+    std::vector<uint8_t> bytes;
+    size_t add(const void *src, size_t n, size_t align = 256) {
+        size_t off = (bytes.size() + align - 1) / align * align;
+        bytes.resize(off + n);
+        if (n && src) memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+};
+
+inline uint32_t range_word(int d, int k) {
+    int nb = d - 32 * k;
+    if (nb <= 0) return 0u;
+    if (nb >= 32) return 0xFFFFFFFFu;
+    return (1u << nb) - 1u;
+}
+
+}  // namespace
+
+extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const int32_t *dsize,
+                           const uint32_t *init_bits, int32_t m, const int32_t *type,
+                           const int32_t *arity, const int64_t *var_off, const int32_t *vars,
+                           const int64_t *par_off, const int64_t *params, const int64_t *tab_off,
+                           const uint32_t *tabs, cubics_prob **out) {
+    if (!out) return fail(CUBICS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(CUBICS_EINVAL, "ctx is NULL");
+    if (n < 0 || m < 0) return fail(CUBICS_EINVAL, "negative n or m");
+    if (n > CUBICS_MAX_VARS) return fail(CUBICS_EUNSUPPORTED, "n=%d exceeds %d variables", n, CUBICS_MAX_VARS);
+    if (n > 0 && (!lo || !dsize)) return fail(CUBICS_EINVAL, "lo/dsize is NULL");
+    if (m > 0 && (!type || !arity || !var_off || !vars || !par_off || !tab_off))
+        return fail(CUBICS_EINVAL, "constraint arrays are NULL");
+    int dmax = 1;
+    for (int i = 0; i < n; ++i) {
+        if (dsize[i] < 1) return fail(CUBICS_EINVAL, "dsize[%d]=%d < 1", i, dsize[i]);
+        if (dsize[i] > CUBICS_MAX_DOMAIN)
+            return fail(CUBICS_EUNSUPPORTED, "dsize[%d]=%d exceeds %d", i, dsize[i], CUBICS_MAX_DOMAIN);
+        if (lo[i] < -(1 << 29) || lo[i] > (1 << 29)) return fail(CUBICS_EUNSUPPORTED, "lo[%d] out of range", i);
+        dmax = std::max(dmax, (int)dsize[i]);
+    }
+    // ALLDIFF scopes compare domains in value space: widen W to their spans
+    int span_words = 1;
+    for (int c = 0; c < m; ++c) {
+        if (type[c] != CUBICS_ALLDIFF) continue;
+        const int k = arity[c];
+        if (k < 1 || var_off[c + 1] - var_off[c] != k) continue;  // reported below
+        const int32_t *sc = vars + var_off[c];
+        bool ok = true;
+        for (int t = 0; t < k; ++t) ok &= sc[t] >= 0 && sc[t] < n;
+        if (!ok) continue;
+        int base = lo[sc[0]], top = lo[sc[0]] + dsize[sc[0]];
+        for (int t = 1; t < k; ++t) {
+            base = std::min(base, (int)lo[sc[t]]);
+            top = std::max(top, (int)(lo[sc[t]] + dsize[sc[t]]));
+        }
+        if (top - base <= CUBICS_MAX_DOMAIN) span_words = std::max(span_words, (top - base + 31) / 32);
+    }
+    const int Win = (dmax + 31) / 32;  // words per row of init_bits
+    const int W = std::max(Win, span_words);
+    if ((int64_t)n * W > 4096) return fail(CUBICS_EUNSUPPORTED, "n*W=%d exceeds 4096 words", n * W);
+    if (m > 0 && (var_off[0] != 0 || par_off[0] != 0 || tab_off[0] != 0))
+        return fail(CUBICS_EINVAL, "offset arrays must start at 0");
+
+    // ---- domains
+    std::vector<uint32_t> dom0((size_t)std::max(n, 1) * W, 0u);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < W; ++k) {
+            uint32_t w = range_word(dsize[i], k);
+            if (init_bits) w &= k < Win ? init_bits[(size_t)i * Win + k] : 0u;
+            dom0[(size_t)i * W + k] = w;
+        }
+
+    // ---- constraints
+    std::vector<Unit> units;
+    std::vector<uint32_t> rows;
+    std::vector<GDesc> gdesc;
+    std::vector<int32_t> gscope;
+    std::vector<int64_t> gcoef;
+    std::vector<int32_t> unary;
+    std::vector<int32_t> deg(std::max(n, 1), 0);
+    std::vector<double> tight_sum(std::max(n, 1), 0.0);
+    bool has_table = false;
+    for (int c = 0; c < m; ++c) {
+        const int ty = type[c], k = arity[c];
+        if (var_off[c + 1] - var_off[c] != k || k < 1)
+            return fail(CUBICS_EINVAL, "constraint %d: arity %d does not match its scope", c, k);
+        const int32_t *sc = vars + var_off[c];
+        for (int t = 0; t < k; ++t) {
+            if (sc[t] < 0 || sc[t] >= n) return fail(CUBICS_EINVAL, "constraint %d: variable %d out of range", c, sc[t]);
+            for (int u = 0; u < t; ++u)
+                if (sc[u] == sc[t]) return fail(CUBICS_EINVAL, "constraint %d: variable %d repeated in scope", c, sc[t]);
+        }
+        const int64_t npar = par_off[c + 1] - par_off[c];
+        const int64_t ntab = tab_off[c + 1] - tab_off[c];
+        if (npar < 0 || ntab < 0) return fail(CUBICS_EINVAL, "constraint %d: decreasing offsets", c);
+        const int64_t *par = params ? params + par_off[c] : nullptr;
+        const uint32_t *tab = tabs ? tabs + tab_off[c] : nullptr;
+        if (ty == CUBICS_UNARY) {
+            if (k != 1) return fail(CUBICS_EINVAL, "constraint %d: UNARY needs arity 1", c);
+            const int i = sc[0], Wi = (dsize[i] + 31) / 32;
+            if (ntab != Wi || !tab) return fail(CUBICS_EINVAL, "constraint %d: UNARY table needs %d words", c, Wi);
+            unary.push_back(i);
+            unary.push_back((int32_t)rows.size());
+            for (int w = 0; w < W; ++w) rows.push_back(w < Wi ? (tab[w] & range_word(dsize[i], w)) : 0u);
+        } else if (ty >= CUBICS_TABLE2 && ty <= CUBICS_QUEENS) {
+            if (k != 2) return fail(CUBICS_EINVAL, "constraint %d: binary type needs arity 2", c);
+            const int i = sc[0], j = sc[1];
+            const int di = dsize[i], dj = dsize[j];
+            deg[i]++; deg[j]++;
+            if (ty == CUBICS_TABLE2) {
+                const int Wj = (dj + 31) / 32;
+                if (ntab != (int64_t)di * Wj || !tab)
+                    return fail(CUBICS_EINVAL, "constraint %d: TABLE2 needs %d x %d words", c, di, Wj);
+                has_table = true;
+                // rows indexed by the value of i (bits over j) and by the value of j (bits over i)
+                const int32_t off_ij = (int32_t)rows.size();
+                rows.resize(rows.size() + (size_t)di * W, 0u);
+                const int32_t off_ji = (int32_t)rows.size();
+                rows.resize(rows.size() + (size_t)dj * W, 0u);
+                int64_t allowed = 0;
+                for (int a = 0; a < di; ++a)
+                    for (int b = 0; b < dj; ++b)
+                        if ((tab[(size_t)a * Wj + b / 32] >> (b % 32)) & 1u) {
+                            rows[off_ij + (size_t)a * W + b / 32] |= 1u << (b % 32);
+                            rows[off_ji + (size_t)b * W + a / 32] |= 1u << (a % 32);
+                            ++allowed;
+                        }
+                const double t = 1.0 - (double)allowed / ((double)di * dj);
+                tight_sum[i] += t; tight_sum[j] += t;
+                units.push_back({i | (U_TABLE << 24), j, off_ij, off_ji});
+                units.push_back({j | (U_TABLE << 24), i, off_ji, off_ij});
+            } else {
+                if (npar != 1 || !par) return fail(CUBICS_EINVAL, "constraint %d: needs 1 parameter", c);
+                const int64_t p = par[0];
+                if (p < -(1LL << 29) || p > (1LL << 29)) return fail(CUBICS_EUNSUPPORTED, "constraint %d: parameter out of range", c);
+                const int32_t dl = (int32_t)((int64_t)lo[j] - lo[i] + (ty == CUBICS_QUEENS ? 0 : p));
+                if (ty == CUBICS_NEQ) {
+                    // x_i != x_j + p: a = b + dl is removed from i; b = a - dl from j
+                    units.push_back({i | (U_NEQ << 24), j, dl, 0});
+                    units.push_back({j | (U_NEQ << 24), i, -dl, 0});
+                    tight_sum[i] += 1.0 / dj; tight_sum[j] += 1.0 / di;
+                } else if (ty == CUBICS_LT) {
+                    units.push_back({i | (U_LT_UB << 24), j, dl, 0});
+                    units.push_back({j | (U_LT_LB << 24), i, dl, 0});
+                    tight_sum[i] += 0.5; tight_sum[j] += 0.5;
+                } else {
+                    const int32_t kq = (int32_t)p;
+                    units.push_back({i | (U_QUEENS << 24), j, kq, (int32_t)(lo[j] - lo[i])});
+                    units.push_back({j | (U_QUEENS << 24), i, kq, (int32_t)(lo[i] - lo[j])});
+                    tight_sum[i] += 3.0 / dj; tight_sum[j] += 3.0 / di;
+                }
+            }
+        } else if (ty == CUBICS_ALLDIFF || ty == CUBICS_LINEAR_LE) {
+            GDesc g;
+            g.type = ty == CUBICS_ALLDIFF ? G_ALLDIFF : G_LINEAR;
+            g.k = k;
+            g.scope_off = (int32_t)gscope.size();
+            g.coef_off = (int32_t)gcoef.size();
+            if (ty == CUBICS_ALLDIFF) {
+                // the scope's domains are compared in value space: base = the
+                // smallest lo; the span must fit the instance's domain words
+                int base = lo[sc[0]], top = lo[sc[0]] + dsize[sc[0]];
+                for (int t = 1; t < k; ++t) {
+                    base = std::min(base, (int)lo[sc[t]]);
+                    top = std::max(top, (int)(lo[sc[t]] + dsize[sc[t]]));
+                }
+                if (top - base > CUBICS_MAX_DOMAIN)
+                    return fail(CUBICS_EUNSUPPORTED, "constraint %d: ALLDIFF value span %d exceeds %d", c,
+                                top - base, CUBICS_MAX_DOMAIN);
+                g.coef_off = base;
+                for (int t = 0; t < k; ++t) tight_sum[sc[t]] += (double)(k - 1) / dsize[sc[t]];
+            } else {
+                if (npar != 1 + k || !par) return fail(CUBICS_EINVAL, "constraint %d: LINEAR_LE needs 1+k parameters", c);
+                double mag = std::fabs((double)par[0]);
+                for (int t = 0; t < k; ++t) {
+                    if (par[1 + t] <= 0) return fail(CUBICS_EINVAL, "constraint %d: non-positive coefficient", c);
+                    const double vmax = std::max(std::fabs((double)lo[sc[t]]), std::fabs((double)lo[sc[t]] + dsize[sc[t]] - 1));
+                    mag += (double)par[1 + t] * vmax;
+                }
+                if (mag > 4.0e18) return fail(CUBICS_EUNSUPPORTED, "constraint %d: linear sum may overflow int64", c);
+                double maxsum = 0;
+                for (int t = 0; t < k; ++t) maxsum += (double)par[1 + t] * ((double)lo[sc[t]] + dsize[sc[t]] - 1);
+                const double tt = maxsum > 0 ? std::min(1.0, std::max(0.0, 1.0 - (double)par[0] / maxsum)) : 0.5;
+                for (int t = 0; t < k; ++t) tight_sum[sc[t]] += tt;
+                for (int t = 0; t <= k; ++t) gcoef.push_back(par[t]);
+            }
+            for (int t = 0; t < k; ++t) {
+                gscope.push_back(sc[t]);
+                deg[sc[t]]++;
+            }
+            gdesc.push_back(g);
+            if (gdesc.size() > 65535) return fail(CUBICS_EUNSUPPORTED, "more than 65535 global constraints");
+        } else {
+            return fail(CUBICS_EINVAL, "constraint %d: unknown type %d", c, ty);
+        }
+    }
+
+    // ---- units sorted by source variable (stable), trigger ranges
+    std::vector<int32_t> trig_off(n + 1, 0);
+    for (const Unit &u : units) trig_off[u.src + 1]++;
+    for (int i = 0; i < n; ++i) trig_off[i + 1] += trig_off[i];
+    std::vector<Unit> sorted(units.size());
+    {
+        std::vector<int32_t> fill(trig_off.begin(), trig_off.end() - 1);
+        for (const Unit &u : units) sorted[fill[u.src]++] = u;
+    }
+    // ---- global trigger lists
+    std::vector<int32_t> gtrig_off(n + 1, 0), gtrig;
+    for (size_t g = 0; g < gdesc.size(); ++g)
+        for (int t = 0; t < gdesc[g].k; ++t) gtrig_off[gscope[gdesc[g].scope_off + t] + 1]++;
+    for (int i = 0; i < n; ++i) gtrig_off[i + 1] += gtrig_off[i];
+    gtrig.resize(std::max<size_t>(gtrig_off[n], 1));
+    {
+        std::vector<int32_t> fill(gtrig_off.begin(), gtrig_off.end() - 1);
+        for (size_t g = 0; g < gdesc.size(); ++g)
+            for (int t = 0; t < gdesc[g].k; ++t) {
+                const int v = gscope[gdesc[g].scope_off + t];
+                gtrig[fill[v]++] = (int32_t)g;
+            }
+    }
+    // ---- static features of the learned policy: degree/(n-1), mean tightness
+    std::vector<float> feat(2 * (size_t)std::max(n, 1), 0.f);
+    for (int i = 0; i < n; ++i) {
+        feat[2 * i] = n > 1 ? (float)deg[i] / (float)(n - 1) : 0.f;
+        feat[2 * i + 1] = deg[i] ? (float)(tight_sum[i] / deg[i]) : 0.f;
+    }
+
+    // ---- pack and upload
+    Packer pk;
+    std::vector<int32_t> lov(lo, lo + n);
+    if (lov.empty()) lov.push_back(0);
+    const size_t o_lo = pk.add(lov.data(), lov.size() * 4);
+    const size_t o_dom0 = pk.add(dom0.data(), dom0.size() * 4);
+    const size_t o_trig = pk.add(trig_off.data(), trig_off.size() * 4);
+    const size_t o_units = pk.add(sorted.data(), std::max<size_t>(sorted.size(), 1) * sizeof(Unit));
+    if (rows.empty()) rows.push_back(0);
+    const size_t o_rows = pk.add(rows.data(), rows.size() * 4);
+    const size_t o_gto = pk.add(gtrig_off.data(), gtrig_off.size() * 4);
+    const size_t o_gt = pk.add(gtrig.data(), gtrig.size() * 4);
+    const size_t o_gd = pk.add(gdesc.data(), std::max<size_t>(gdesc.size(), 1) * sizeof(GDesc));
+    if (gscope.empty()) gscope.push_back(0);
+    const size_t o_gs = pk.add(gscope.data(), gscope.size() * 4);
+    if (gcoef.empty()) gcoef.push_back(0);
+    const size_t o_gc = pk.add(gcoef.data(), gcoef.size() * 8);
+    if (unary.empty()) { unary.push_back(0); unary.push_back(0); }
+    const size_t o_un = pk.add(unary.data(), unary.size() * 4);
+    const size_t o_ft = pk.add(feat.data(), feat.size() * 4);
+
+    HIPCHK(hipSetDevice(ctx->device));
+    void *blob = nullptr;
+    if (hipMalloc(&blob, pk.bytes.size()) != hipSuccess)
+        return fail(CUBICS_ENOMEM, "hipMalloc(%zu) for the problem failed", pk.bytes.size());
+    hipError_t e = hipMemcpyAsync(blob, pk.bytes.data(), pk.bytes.size(), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(blob);
+        return fail(CUBICS_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    cubics_prob *p = new cubics_prob();
+    p->ctx = ctx;
+    p->blob = blob;
+    p->n = n;
+    p->W = W;
+    p->dmax = dmax;
+    p->n_units = (int)sorted.size();
+    p->n_glob = (int)gdesc.size();
+    p->has_table = has_table;
+    char *b8 = (char *)blob;
+    InstDev &I = p->dev;
+    memset(&I, 0, sizeof I);
+    I.n = n;
+    I.W = W;
+    int S = 8;
+    while (S < dmax && S < 64) S *= 2;
+    I.S = S;
+    I.dmax = dmax;
+    I.n_units = p->n_units;
+    I.n_glob = p->n_glob;
+    {
+        int nu = 0;
+        for (int c = 0; c < m; ++c) nu += type[c] == CUBICS_UNARY;
+        I.n_unary = nu;
+    }
+    I.seg_ok = (dmax <= 64) ? 1 : 0;
+    I.lo = (const int32_t *)(b8 + o_lo);
+    I.dom0 = (const uint32_t *)(b8 + o_dom0);
+    I.trig_off = (const int32_t *)(b8 + o_trig);
+    I.units = (const Unit *)(b8 + o_units);
+    I.rows = (const uint32_t *)(b8 + o_rows);
+    I.gtrig_off = (const int32_t *)(b8 + o_gto);
+    I.gtrig = (const int32_t *)(b8 + o_gt);
+    I.gdesc = (const GDesc *)(b8 + o_gd);
+    I.gscope = (const int32_t *)(b8 + o_gs);
+    I.gcoef = (const int64_t *)(b8 + o_gc);
+    I.unary = (const int32_t *)(b8 + o_un);
+    I.feat_static = (const float *)(b8 + o_ft);
+    char key[160];
+    snprintf(key, sizeof key, "W%d_d%d_n%d_g%d_t%d", W, (dmax + 7) / 8 * 8, (n + 15) / 16 * 16,
+             p->n_glob > 0, has_table ? 1 : 0);
+    p->bucket = key;
+    *out = p;
+    return CUBICS_OK;
+}
+
+extern "C" void cubics_free(cubics_prob *p) {
+    if (!p) return;
+    if (p->blob) {
+        (void)hipSetDevice(p->ctx->device);
+        (void)hipFree(p->blob);
+    }
+    delete p;
+}
+
+extern "C" int cubics_prob_info(const cubics_prob *p, int32_t *n, int32_t *W, int32_t *n_units, int32_t *n_global) {
+    if (!p) return fail(CUBICS_EINVAL, "prob is NULL");
+    if (n) *n = p->n;
+    if (W) *W = p->W;
+    if (n_units) *n_units = p->n_units;
+    if (n_global) *n_global = p->n_glob;
+    return CUBICS_OK;
+}
+
+// ------------------------------------------------------------ solve support
+int policy_fill(const cubics_policy *pol, PolicyDev *out);
+
+namespace {
+
+int pow2_ge(int x) {
+    int p = 1;
+    while (p < x) p *= 2;
+    return p;
+}
+
+struct Geometry {
+    int nmax = 1, wmax = 1, gmax = 0;
+    int lds_words = 0;
+};
+
+Geometry geometry(cubics_prob *const *probs, int B) {
+    Geometry g;
+    int wm = 1;
+    for (int b = 0; b < B; ++b) {
+        g.nmax = std::max(g.nmax, probs[b]->n);
+        wm = std::max(wm, probs[b]->W);
+        g.gmax = std::max(g.gmax, probs[b]->n_glob);
+    }
+    g.wmax = wm <= 1 ? 1 : wm <= 2 ? 2 : wm <= 4 ? 4 : 8;
+    const int ndw = (g.nmax + 63) / 64, ngw = std::max((g.gmax + 63) / 64, 1);
+    int words = ((g.nmax * g.wmax) + 1) & ~1;
+    words += 2 * ndw + 2 * ndw + 2 * ngw + 32;
+    g.lds_words = (words + 1) & ~1;
+    return g;
+}
+
+int choose_layout(cubics_prob *const *probs, int B, int requested) {
+    if (requested == CUBICS_LAYOUT_LANE || requested == CUBICS_LAYOUT_SEG) return requested;
+    // AUTO: the autotuned choice of the first instance's shape bucket, else a
+    // rule: lane-per-value segments pay off once domains are wide
+    cubics_ctx *ctx = probs[0]->ctx;
+    auto it = ctx->tuned.find(probs[0]->bucket);
+    if (it != ctx->tuned.end()) return it->second;
+    int dmax = 1;
+    bool seg_ok = true;
+    for (int b = 0; b < B; ++b) {
+        dmax = std::max(dmax, probs[b]->dmax);
+        seg_ok &= probs[b]->dmax <= 64;
+    }
+    return (seg_ok && dmax > 24) ? CUBICS_LAYOUT_SEG : CUBICS_LAYOUT_LANE;
+}
+
+}  // namespace
+
+static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_limits *lims,
+                      cubics_result *results) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!probs || B < 1 || !results) return fail(CUBICS_EINVAL, "bad batch arguments");
+    if (mode < 0 || mode > 2) return fail(CUBICS_EINVAL, "bad mode %d", mode);
+    for (int b = 0; b < B; ++b)
+        if (!probs[b]) return fail(CUBICS_EINVAL, "prob[%d] is NULL", b);
+    cubics_ctx *ctx = probs[0]->ctx;
+    for (int b = 1; b < B; ++b)
+        if (probs[b]->ctx->device != ctx->device) return fail(CUBICS_EINVAL, "problems on different devices");
+    cubics_limits dflt;
+    memset(&dflt, 0, sizeof dflt);
+    dflt.donate = 1;
+    const cubics_limits &L0 = lims ? lims[0] : dflt;
+    if (L0.branching == CUBICS_BRANCH_LEARNED && !L0.policy)
+        return fail(CUBICS_EINVAL, "LEARNED branching needs a policy");
+    if (L0.branching != CUBICS_BRANCH_FIRST_FAIL && L0.branching != CUBICS_BRANCH_LEARNED)
+        return fail(CUBICS_EINVAL, "bad branching %d", L0.branching);
+    if (L0.split_target < 0 || L0.time_ms < 0 || L0.workers < 0)
+        return fail(CUBICS_EINVAL, "negative split_target / time_ms / workers");
+    for (int b = 0; b < B; ++b) {
+        const cubics_limits &Lb = lims ? lims[b] : dflt;
+        if (Lb.sol_capacity > 0 && !Lb.sol_buf) return fail(CUBICS_EINVAL, "sol_capacity > 0 with NULL sol_buf");
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t st = ctx->stream;
+    const Geometry G = geometry(probs, B);
+    const int layout = choose_layout(probs, B, L0.layout);
+
+    // ---- workers: fill the device with co-resident wavefronts
+    int wpb = 4;
+    size_t lds = (size_t)G.lds_words * 4 * wpb;
+    while (wpb > 1 && lds > 64 * 1024) {
+        wpb /= 2;
+        lds = (size_t)G.lds_words * 4 * wpb;
+    }
+    if (lds > 64 * 1024) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", lds);
+    int bpc = 0;
+    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds));
+    if (bpc < 1) bpc = 1;
+    int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
+    const int blocks = (nworkers + wpb - 1) / wpb;
+
+    // ---- buffers
+    const uint32_t frame_words = (uint32_t)((FRAME_HDR + G.nmax * G.wmax + 15) / 16 * 16);
+    const uint32_t slot_words = (uint32_t)((SLOT_HDR + G.nmax * G.wmax + 15) / 16 * 16);
+    const uint32_t trail_words = frame_words * (uint32_t)(G.nmax + 1);
+    long long want = (long long)B + 2LL * nworkers + 2LL * L0.split_target + 1024;
+    if (want > (1LL << 26)) want = 1LL << 26;
+    uint32_t cap = 4096;
+    while ((long long)cap < want) cap *= 2;
+    int rc;
+    if ((rc = ctx->inst.ensure(sizeof(InstDev) * (size_t)B))) return rc;
+    if ((rc = ctx->ctl.ensure(sizeof(InstCtl) * (size_t)B))) return rc;
+    if ((rc = ctx->q.ensure(sizeof(QCtl)))) return rc;
+    if ((rc = ctx->qseq.ensure(4ull * cap))) return rc;
+    if ((rc = ctx->qdata.ensure(4ull * cap * slot_words))) return rc;
+    if ((rc = ctx->trail.ensure(4ull * trail_words * (size_t)nworkers))) return rc;
+
+    std::vector<InstDev> inst(B);
+    for (int b = 0; b < B; ++b) {
+        const cubics_limits &Lb = lims ? lims[b] : dflt;
+        inst[b] = probs[b]->dev;
+        inst[b].sol_buf = Lb.sol_buf;
+        inst[b].sol_cap = Lb.sol_buf ? Lb.sol_capacity : 0;
+        inst[b].max_nodes = Lb.max_nodes;
+        inst[b].max_solutions = Lb.max_solutions;
+        if (mode == CUBICS_MODE_FIRST && inst[b].sol_cap > 1) inst[b].sol_cap = 1;
+    }
+    HIPCHK(hipMemcpyAsync(ctx->inst.p, inst.data(), sizeof(InstDev) * B, hipMemcpyHostToDevice, st));
+
+    SearchParams P;
+    memset(&P, 0, sizeof P);
+    P.inst = (const InstDev *)ctx->inst.p;
+    P.ctl = (InstCtl *)ctx->ctl.p;
+    P.B = B;
+    P.mode = mode;
+    P.layout = layout;
+    P.branching = L0.branching;
+    P.q = (QCtl *)ctx->q.p;
+    P.qseq = (uint32_t *)ctx->qseq.p;
+    P.qdata = (uint32_t *)ctx->qdata.p;
+    P.qmask = cap - 1;
+    P.slot_words = slot_words;
+    P.trail = (uint32_t *)ctx->trail.p;
+    P.frame_words = frame_words;
+    P.trail_words = trail_words;
+    P.nworkers = nworkers;
+    P.donate = L0.donate ? 1 : 0;
+    P.split_target = L0.split_target;
+    P.time_ticks = L0.time_ms > 0 ? (long long)L0.time_ms * ctx->wall_khz : 0;
+    P.cancel = ctx->cancel_host;
+    P.lds_words = G.lds_words;
+    P.nmax = G.nmax;
+    P.wmax = G.wmax;
+    P.gmax = G.gmax;
+    if (L0.policy) policy_fill(L0.policy, &P.policy);
+    __atomic_store_n(ctx->cancel_host, 0, __ATOMIC_RELEASE);
+
+    HIPCHK(launch_init(P, st));
+    HIPCHK(hipEventRecord(ctx->ev0, st));
+    HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, st));
+    HIPCHK(hipEventRecord(ctx->ev1, st));
+    std::vector<InstCtl> ctl(B);
+    QCtl qh;
+    HIPCHK(hipMemcpyAsync(ctl.data(), ctx->ctl.p, sizeof(InstCtl) * B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&qh, ctx->q.p, sizeof(QCtl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float kms = 0.f;
+    HIPCHK(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+
+    for (int b = 0; b < B; ++b) {
+        const cubics_limits &Lb = lims ? lims[b] : dflt;
+        const InstCtl &c = ctl[b];
+        cubics_result &r = results[b];
+        memset(&r, 0, sizeof r);
+        r.nodes = c.nodes;
+        r.fails = c.fails;
+        r.revisions = c.revisions;
+        r.steals = c.steals;
+        r.alg_bytes = c.alg_bytes;
+        r.tasks = c.tasks;
+        r.ms = ms;
+        r.kernel_ms = kms;
+        const bool stopped = qh.stop != 0;
+        const int stop_verdict = qh.stop_reason == 3 ? CUBICS_CANCELLED : CUBICS_LIMIT;
+        if (mode == CUBICS_MODE_FIRST) {
+            if (c.found) {
+                r.verdict = CUBICS_SAT;
+                r.count = 1;
+                r.n_written = inst[b].sol_cap > 0 ? 1 : 0;
+            } else if (c.reason == 2) {
+                r.verdict = CUBICS_LIMIT;
+            } else if (stopped) {
+                r.verdict = stop_verdict;
+            } else {
+                r.verdict = CUBICS_UNSAT;
+            }
+        } else {
+            uint64_t count = c.count + c.n_slots;
+            r.n_written = std::min<uint64_t>(c.n_slots, inst[b].sol_cap);
+            r.truncated = (inst[b].sol_cap > 0 && c.n_slots > inst[b].sol_cap) ? 1 : 0;
+            if (c.reason == 3 || (Lb.max_solutions && count >= Lb.max_solutions)) {
+                count = std::min<uint64_t>(count, Lb.max_solutions);
+                r.verdict = CUBICS_LIMIT;
+            } else if (c.reason == 2) {
+                r.verdict = CUBICS_LIMIT;
+            } else if (stopped) {
+                r.verdict = stop_verdict;
+            } else {
+                r.verdict = count > 0 ? CUBICS_SAT : CUBICS_UNSAT;
+            }
+            r.count = count;
+        }
+    }
+    return CUBICS_OK;
+}
+
+extern "C" int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits, cubics_result *result) {
+    if (!prob) return fail(CUBICS_EINVAL, "prob is NULL");
+    cubics_prob *arr[1] = {prob};
+    return solve_impl(arr, 1, mode, limits, result);
+}
+
+extern "C" int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
+                                  cubics_result *results) {
+    return solve_impl(probs, B, mode, limits, results);
+}
+
+extern "C" int cubics_root(cubics_prob *p, int32_t layout, uint32_t *out_bits, int32_t *failed) {
+    if (!p || !out_bits || !failed) return fail(CUBICS_EINVAL, "NULL argument");
+    cubics_ctx *ctx = p->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    cubics_prob *arr[1] = {p};
+    const Geometry G = geometry(arr, 1);
+    const size_t nw = (size_t)std::max(p->n, 1) * p->W;
+    int rc;
+    if ((rc = ctx->inst.ensure(sizeof(InstDev)))) return rc;
+    if ((rc = ctx->rootout.ensure(nw * 4 + 64))) return rc;
+    HIPCHK(hipMemcpyAsync(ctx->inst.p, &p->dev, sizeof(InstDev), hipMemcpyHostToDevice, ctx->stream));
+    SearchParams P;
+    memset(&P, 0, sizeof P);
+    P.inst = (const InstDev *)ctx->inst.p;
+    P.layout = choose_layout(arr, 1, layout);
+    P.lds_words = G.lds_words;
+    P.nmax = G.nmax;
+    P.wmax = G.wmax;
+    P.gmax = G.gmax;
+    uint32_t *dout = (uint32_t *)ctx->rootout.p;
+    int32_t *dfail = (int32_t *)((char *)ctx->rootout.p + nw * 4);
+    unsigned long long *drev = (unsigned long long *)((char *)ctx->rootout.p + nw * 4 + 8);
+    HIPCHK(launch_root(G.wmax, P, dout, dfail, drev, (size_t)G.lds_words * 4, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out_bits, dout, (size_t)p->n * p->W * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(failed, dfail, 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return CUBICS_OK;
+}

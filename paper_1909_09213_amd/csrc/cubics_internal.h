@@ -1,0 +1,127 @@
+// Internal data layout shared by the host packer (cubics_host.cpp) and the
+// HIP kernels (cubics_search.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace cubics {
+
+// Propagator ("unit") types of binary constraints, one unit per direction.
+// A unit revises its target variable against its source variable.
+enum UnitType : int32_t {
+    U_TABLE = 1,   // extensional table, rows in both orientations
+    U_NEQ = 2,     // remove a = b + p0 when D_src = {b}
+    U_LT_UB = 3,   // keep a <= max(D_src) + p0 - 1
+    U_LT_LB = 4,   // keep a >= min(D_src) - p0 + 1
+    U_QUEENS = 5,  // p0 = k, p1 = delta: a conflicts with b iff a - b - delta in {0, k, -k}
+};
+enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2 };
+enum TaskKind : int32_t { K_ROOT = 0, K_NODE = 1, K_FRAME = 2 };
+
+// Binary unit (16 B).  tt = target var | type << 24.
+// TABLE: p0 = word offset of rows indexed by target value (bits over source),
+//        p1 = word offset of rows indexed by source value (bits over target).
+struct Unit {
+    int32_t tt;
+    int32_t src;
+    int32_t p0;
+    int32_t p1;
+};
+
+// Global constraint descriptor (16 B).
+struct GDesc {
+    int32_t type;
+    int32_t k;         // arity
+    int32_t scope_off; // into gscope
+    int32_t coef_off;  // into gcoef: b, a_0..a_{k-1} (LINEAR)
+};
+
+// Per-instance read-only descriptor (device memory).  All pointers are device
+// pointers into the problem's packed blob.
+struct InstDev {
+    int32_t n, W, S, dmax;       // vars, words/domain, SEG lanes per unit, max domain
+    int32_t n_units, n_glob, n_unary, seg_ok;
+    const int32_t *lo;           // [n]
+    const uint32_t *dom0;        // [n*W] declared ranges intersected with init bits
+    const int32_t *trig_off;     // [n+1] units sorted by source var
+    const Unit *units;           // [n_units]
+    const uint32_t *rows;        // table rows (W words per row)
+    const int32_t *gtrig_off;    // [n+1]
+    const int32_t *gtrig;        // global ids watching each var
+    const GDesc *gdesc;          // [n_glob]
+    const int32_t *gscope;
+    const int64_t *gcoef;
+    const int32_t *unary;        // [n_unary][2] {var, row word offset}
+    const float *feat_static;    // [n][2] static features for the learned policy
+    // per-instance solve settings (written by the host for each solve)
+    int32_t *sol_buf;
+    uint64_t sol_cap;
+    uint64_t max_nodes;
+    uint64_t max_solutions;
+};
+
+// Per-instance mutable solve state (device memory, zeroed before a solve).
+struct InstCtl {
+    unsigned long long count, n_slots, nodes, fails, revisions, alg_bytes, steals, tasks;
+    int32_t done;     // 1 = stop working on this instance
+    int32_t reason;   // 0 none, 1 first found, 2 node limit, 3 cap
+    int32_t found;    // FIRST mode winner flag
+    int32_t pad;
+};
+
+// Work-queue control block: each hot word on its own 128-byte line.
+struct QCtl {
+    uint32_t head; uint32_t _p0[31];
+    uint32_t tail; uint32_t _p1[31];
+    int32_t pending; int32_t _p2[31];
+    int32_t idle; int32_t _p3[31];
+    unsigned long long produced; uint32_t _p4[30];
+    int32_t stop; int32_t stop_reason; uint32_t _p5[30];
+};
+
+// Queue slot / trail frame header layout (uint32 words).
+constexpr int SLOT_HDR = 16;   // [0] inst [1] kind [2] x [3] depth [4..12) vals
+constexpr int FRAME_HDR = 16;  // [0] x [1] depth [4..12) vals
+
+// Learned policy (device).
+constexpr int POLICY_F = 8;    // features per variable (5 used, zero padded)
+constexpr int POLICY_H = 64;   // hidden units
+
+struct PolicyDev {
+    const uint16_t *w1;  // [H][F] bf16 (row h = weights of hidden unit h)
+    const float *b1;     // [H]
+    const uint16_t *w2;  // [H] bf16
+    float b2;
+    int32_t F, H;
+};
+
+struct SearchParams {
+    const InstDev *inst;
+    InstCtl *ctl;
+    int32_t B;
+    int32_t mode;
+    int32_t layout;      // 1 LANE, 2 SEG
+    int32_t branching;
+    QCtl *q;
+    uint32_t *qseq;
+    uint32_t *qdata;
+    uint32_t qmask;
+    uint32_t slot_words;
+    uint32_t *trail;
+    uint32_t frame_words;
+    uint32_t trail_words;  // per worker
+    int32_t nworkers;
+    int32_t donate;
+    long long split_target;
+    long long time_ticks;  // 0 = none (wall clock ticks)
+    const volatile int32_t *cancel;
+    int32_t lds_words;     // per worker
+    int32_t nmax, wmax, gmax;
+    PolicyDev policy;
+    float *trace_out;      // optional trace recording (learned policy training)
+    unsigned long long *trace_count;
+    long long trace_cap;
+    int32_t trace_stride;  // ε-exploration rate denominator (0 = off)
+    uint32_t seed;
+};
+
+}  // namespace cubics

@@ -1,0 +1,1269 @@
+// HIP kernels of the CSP solver for gfx950 (CDNA4, wave64).
+//
+// One wavefront is one search worker.  A worker keeps the domains of its
+// current node as word-packed bitsets in LDS (bit a of variable i = value
+// lo_i + a), revises constraints to a fixpoint with 64 lanes at a time,
+// tests the node with ballots and wave reductions, and backtracks through a
+// private trail of domain snapshots in HBM (the paper's per-domain
+// save/restore stacks, Sec. 2.2).  Workers take subtrees from a global
+// lock-free work queue and donate their shallowest open subtree when others
+// are idle, so the whole search stays on the GPU (Sec. 2.1).
+//
+// Propagation (Sec. 1.1 "constraint propagation", parallelised as in
+// Sec. 2.2): every constraint is split into propagators.  A binary
+// constraint gives two directed units, each revising its target variable
+// against its source; all-different and linear-sum constraints are revised
+// by the whole wave.  A round revises every unit whose source changed in the
+// previous round; rounds repeat until nothing changes or a domain empties.
+// Domain removals are atomic ANDs on LDS words, so units of one round may run
+// in any order: all propagators are monotone, and the fixpoint they reach is
+// unique, hence identical to the oracle's.
+//
+// Binary units run in one of two layouts:
+//   LANE: one lane per unit; the lane ORs the support rows of the source's
+//         live values (rows indexed by source value give the allowed target
+//         values) and ANDs the union into the target.
+//   SEG:  S = pow2 >= dmax lanes per unit, one lane per target value; each
+//         lane tests its value's support row against the source domain and a
+//         64-lane ballot assembles the new target words.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cubics_internal.h"
+
+namespace cubics {
+
+#define DEV __device__ __forceinline__
+
+typedef unsigned long long u64;
+
+DEV int lane_id() { return __lane_id(); }
+// Order LDS traffic between the lanes of one wave (compiler barrier + wait).
+DEV void wsync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup"); }
+DEV int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+DEV uint32_t uniu(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+DEV u64 uni64(u64 x) {
+    uint32_t lo = uniu((uint32_t)x), hi = uniu((uint32_t)(x >> 32));
+    return ((u64)hi << 32) | lo;
+}
+DEV long long unill(long long x) { return (long long)uni64((u64)x); }
+
+DEV uint32_t wave_or(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+DEV int wave_sum(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+DEV long long wave_sum64(long long v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+DEV u64 wave_sumu64(u64 v) { return (u64)wave_sum64((long long)v); }
+DEV uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        uint32_t w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+// -------------------------------------------------------------- atomics
+DEV uint32_t ld_acq(uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV uint32_t ld_rlx(uint32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV int ld_rlx_i(int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV u64 ld_rlx_u64(u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void st_rel(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV void st_rel_i(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV int add_i(int32_t *p, int v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV u64 add_u64(u64 *p, u64 v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV bool cas_u32(uint32_t *p, uint32_t *expected, uint32_t desired) {
+    return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_ACQ_REL,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV bool cas_i(int32_t *p, int expected, int desired) {
+    return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------- bit helpers
+template <int WM>
+DEV int pop_w(const uint32_t (&d)[WM], int W) {
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if (k < W) s += __popc(d[k]);
+    return s;
+}
+template <int WM>
+DEV int low_w(const uint32_t (&d)[WM], int W) {  // lowest set index, -1 if empty
+    int r = -1;
+#pragma unroll
+    for (int k = WM - 1; k >= 0; --k)
+        if (k < W && d[k]) r = 32 * k + __ffs(d[k]) - 1;
+    return r;
+}
+template <int WM>
+DEV int high_w(const uint32_t (&d)[WM], int W) {  // highest set index, -1 if empty
+    int r = -1;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if (k < W && d[k]) r = 32 * k + 31 - __clz(d[k]);
+    return r;
+}
+// mask of indices <= ub (ub may be negative or >= 32W)
+DEV uint32_t mask_le(int ub, int k) {
+    int t = ub - 32 * k;
+    if (t < 0) return 0u;
+    if (t >= 31) return 0xFFFFFFFFu;
+    return (2u << t) - 1u;
+}
+// mask of indices >= lb
+DEV uint32_t mask_ge(int lb, int k) {
+    int t = lb - 32 * k;
+    if (t <= 0) return 0xFFFFFFFFu;
+    if (t >= 32) return 0u;
+    return ~((1u << t) - 1u);
+}
+DEV uint32_t bit_in_word(int idx, int k) {  // word k of the singleton {idx}; idx may be out of range
+    return (idx >= 32 * k && idx < 32 * k + 32) ? (1u << (idx - 32 * k)) : 0u;
+}
+
+// ------------------------------------------------------------ counters
+struct Counters {
+    u64 nodes, fails, sols, steals, tasks;  // wave-uniform
+    u64 rev, bytes;                         // per lane
+};
+
+// ------------------------------------------------- binary unit revisions
+
+// LANE layout: full new target words for one unit.
+template <int WM>
+DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
+                     const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W) {
+    const int ty = u.tt >> 24;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) nw[k] = dt[k];
+    if (ty == U_TABLE) {
+        uint32_t acc[WM];
+#pragma unroll
+        for (int k = 0; k < WM; ++k) acc[k] = 0u;
+        const uint32_t *rows = I.rows + u.p1;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            if (w >= W) break;
+            uint32_t bits = ds[w];
+            while (bits) {
+                int b = 32 * w + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const uint32_t *r = rows + (size_t)b * W;
+#pragma unroll
+                for (int k = 0; k < WM; ++k)
+                    if (k < W) acc[k] |= r[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
+    } else if (ty == U_NEQ) {
+        if (pop_w(ds, W) == 1) {
+            int a = low_w(ds, W) + u.p0;
+#pragma unroll
+            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & ~bit_in_word(a, k);
+        }
+    } else if (ty == U_LT_UB) {
+        int ub = high_w(ds, W) + u.p0 - 1;
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & mask_le(ub, k);
+    } else if (ty == U_LT_LB) {
+        int lb = low_w(ds, W) - u.p0 + 1;
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & mask_ge(lb, k);
+    } else if (ty == U_QUEENS) {
+        if (pop_w(ds, W) <= 3) {
+            // unsupported = intersection over b in D_src of {b+d, b+d+k, b+d-k}
+            uint32_t uns[WM];
+#pragma unroll
+            for (int k = 0; k < WM; ++k) uns[k] = 0xFFFFFFFFu;
+            const int kk = u.p0, dl = u.p1;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (w >= W) break;
+                uint32_t bits = ds[w];
+                while (bits) {
+                    int b = 32 * w + __ffs(bits) - 1 + dl;
+                    bits &= bits - 1;
+#pragma unroll
+                    for (int k = 0; k < WM; ++k)
+                        uns[k] &= bit_in_word(b, k) | bit_in_word(b + kk, k) | bit_in_word(b - kk, k);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & ~uns[k];
+        }
+    }
+}
+
+// SEG layout: is target value index a supported by the source domain?
+template <int WM>
+DEV bool supported_seg(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM], int a, int W) {
+    const int ty = u.tt >> 24;
+    if (ty == U_TABLE) {
+        const uint32_t *r = I.rows + u.p0 + (size_t)a * W;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k < W) acc |= r[k] & ds[k];
+        return acc != 0;
+    } else if (ty == U_NEQ) {
+        return !(pop_w(ds, W) == 1 && low_w(ds, W) + u.p0 == a);
+    } else if (ty == U_LT_UB) {
+        return a <= high_w(ds, W) + u.p0 - 1;
+    } else if (ty == U_LT_LB) {
+        return a >= low_w(ds, W) - u.p0 + 1;
+    } else {  // QUEENS: some b in D_src outside {a-d, a-d-k, a-d+k}
+        const int b0 = a - u.p1;
+        int cnt = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k < W)
+                cnt += __popc(ds[k] & ~(bit_in_word(b0, k) | bit_in_word(b0 - u.p0, k) |
+                                        bit_in_word(b0 + u.p0, k)));
+        return cnt > 0;
+    }
+}
+
+// algorithmic bytes of one binary revision: both domains, the support rows of
+// the target's live values for a table, and the target written back if changed
+DEV u64 rev_bytes(int ty, int W, int pop_t, bool changed) {
+    u64 b = 8ull * W + (changed ? 4ull * W : 0ull);
+    if (ty == U_TABLE) b += 4ull * (u64)pop_t * (u64)W;
+    return b;
+}
+
+// LDS view of one worker.
+struct Lds {
+    uint32_t *dom;   // [nmax * wmax]
+    u64 *dA, *dB;    // dirty sets [ndw]
+    u64 *gp;         // pending globals [ngw]
+    uint32_t *scr;   // 32 words scratch
+};
+
+// Process one chunk of binary units in LANE layout.  Returns wave-uniform fail.
+template <int WM>
+DEV bool chunk_lane(const InstDev &I, const Lds &L, u64 *nxt, int my_u, Counters &C, int lane) {
+    const int W = I.W;
+    bool changed = false;
+    int tgt = 0;
+    if (my_u >= 0) {
+        const Unit u = I.units[my_u];
+        tgt = u.tt & 0xFFFFFF;
+        uint32_t ds[WM], dt[WM], nw[WM];
+#pragma unroll
+        for (int k = 0; k < WM; ++k) {
+            ds[k] = k < W ? L.dom[u.src * W + k] : 0u;
+            dt[k] = k < W ? L.dom[tgt * W + k] : 0u;
+        }
+        revise_lane<WM>(I, u, ds, dt, nw, W);
+#pragma unroll
+        for (int k = 0; k < WM; ++k) changed |= (k < W) && nw[k] != dt[k];
+        C.rev += 1;
+        C.bytes += rev_bytes(u.tt >> 24, W, pop_w(dt, W), changed);
+        if (changed) {
+#pragma unroll
+            for (int k = 0; k < WM; ++k)
+                if (k < W && nw[k] != dt[k]) atomicAnd(&L.dom[tgt * W + k], nw[k]);
+            atomicOr(&nxt[tgt >> 6], 1ull << (tgt & 63));
+        }
+    }
+    wsync();
+    bool empty = false;
+    if (changed) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k < W) acc |= L.dom[tgt * W + k];
+        empty = acc == 0;
+    }
+    return __ballot(empty) != 0;
+}
+
+// Process one chunk of binary units in SEG layout (W <= 2, S lanes per unit).
+template <int WM>
+DEV bool chunk_seg(const InstDev &I, const Lds &L, u64 *nxt, int my_u, int sh, Counters &C, int lane) {
+    const int W = I.W;
+    const int S = 1 << sh;
+    const int slot = lane >> sh, a = lane & (S - 1);
+    bool sup = false;
+    Unit u = {0, 0, 0, 0};
+    uint32_t dt[WM];
+#pragma unroll
+    for (int k = 0; k < WM; ++k) dt[k] = 0u;
+    if (my_u >= 0) {
+        u = I.units[my_u];
+        const int tgt = u.tt & 0xFFFFFF;
+        uint32_t ds[WM];
+#pragma unroll
+        for (int k = 0; k < WM; ++k) {
+            ds[k] = k < W ? L.dom[u.src * W + k] : 0u;
+            dt[k] = k < W ? L.dom[tgt * W + k] : 0u;
+        }
+        const bool live = (a < 32 * W) && ((dt[a >> 5] >> (a & 31)) & 1u);
+        if (live) sup = supported_seg<WM>(I, u, ds, a, W);
+    }
+    const u64 m = __ballot(sup);
+    bool changed = false;
+    int tgt = u.tt & 0xFFFFFF;
+    if (my_u >= 0 && a == 0) {
+        const u64 seg = sh == 6 ? m : ((m >> (slot << sh)) & ((1ull << S) - 1ull));
+        uint32_t nw[WM];
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = k == 0 ? (uint32_t)seg : (k == 1 ? (uint32_t)(seg >> 32) : 0u);
+#pragma unroll
+        for (int k = 0; k < WM; ++k) changed |= (k < W) && nw[k] != dt[k];
+        C.rev += 1;
+        C.bytes += rev_bytes(u.tt >> 24, W, pop_w(dt, W), changed);
+        if (changed) {
+#pragma unroll
+            for (int k = 0; k < WM; ++k)
+                if (k < W && nw[k] != dt[k]) atomicAnd(&L.dom[tgt * W + k], nw[k]);
+            atomicOr(&nxt[tgt >> 6], 1ull << (tgt & 63));
+        }
+    }
+    wsync();
+    bool empty = false;
+    if (changed) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k < W) acc |= L.dom[tgt * W + k];
+        empty = acc == 0;
+    }
+    return __ballot(empty) != 0;
+}
+
+// ----------------------------------------------------- global revisions
+
+// value-space shifts of W-word bitsets (bit a -> bit a + s, and back)
+template <int WM>
+DEV void shl_w(const uint32_t (&d)[WM], int s, uint32_t (&o)[WM]) {
+    const int q = s >> 5, r = s & 31;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        uint32_t hi = 0u, lo = 0u;
+#pragma unroll
+        for (int j = 0; j < WM; ++j) {
+            hi = (j == k - q) ? d[j] : hi;
+            lo = (j == k - q - 1) ? d[j] : lo;
+        }
+        o[k] = r ? ((hi << r) | (lo >> (32 - r))) : hi;
+    }
+}
+template <int WM>
+DEV void shr_w(const uint32_t (&d)[WM], int s, uint32_t (&o)[WM]) {
+    const int q = s >> 5, r = s & 31;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        uint32_t lo = 0u, hi = 0u;
+#pragma unroll
+        for (int j = 0; j < WM; ++j) {
+            lo = (j == k + q) ? d[j] : lo;
+            hi = (j == k + q + 1) ? d[j] : hi;
+        }
+        o[k] = r ? ((lo >> r) | (hi << (32 - r))) : lo;
+    }
+}
+
+// All-different: the values of singleton scope variables are removed from the
+// other scope variables (two singletons with one value fail); then the union
+// of the scope domains must hold at least k values.  Domains are aligned in
+// value space: bit a of variable v stands for value lo_v + a, i.e. bit
+// a + (lo_v - base) of the union, with base = the smallest lo of the scope.
+template <int WM>
+DEV bool revise_alldiff(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt, Counters &C, int lane) {
+    const int W = I.W, k = g.k, base = g.coef_off;
+    const int32_t *sc = I.gscope + g.scope_off;
+    uint32_t U[WM];
+    int nsing = 0;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) U[w] = 0u;
+    for (int t = lane; t < k; t += 64) {
+        const int v = sc[t];
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        if (pop_w(d, W) == 1) {
+            ++nsing;
+            const int sft = I.lo[v] - base;
+            if (sft) {
+                uint32_t e[WM];
+                shl_w(d, sft, e);
+#pragma unroll
+                for (int w = 0; w < WM; ++w) U[w] |= e[w];
+            } else {
+#pragma unroll
+                for (int w = 0; w < WM; ++w) U[w] |= d[w];
+            }
+        }
+    }
+    int upop = 0;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) {
+        if (w < W) {
+            U[w] = wave_or(U[w]);
+            upop += __popc(U[w]);
+        }
+    }
+    nsing = wave_sum(nsing);
+    C.rev += lane == 0 ? 1 : 0;
+    C.bytes += lane == 0 ? 4ull * (u64)k * W : 0ull;
+    if (upop < nsing) return true;  // two singletons share a value
+    uint32_t Un[WM];
+    bool emp = false;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) Un[w] = 0u;
+    for (int t = lane; t < k; t += 64) {
+        const int v = sc[t];
+        const int sft = I.lo[v] - base;
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        if (pop_w(d, W) >= 2) {
+            uint32_t Uv[WM];
+            if (sft) {
+                shr_w(U, sft, Uv);
+            } else {
+#pragma unroll
+                for (int w = 0; w < WM; ++w) Uv[w] = U[w];
+            }
+            bool ch = false;
+            uint32_t any = 0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (w < W) {
+                    uint32_t nd = d[w] & ~Uv[w];
+                    ch |= nd != d[w];
+                    d[w] = nd;
+                    any |= nd;
+                }
+            }
+            if (ch) {
+#pragma unroll
+                for (int w = 0; w < WM; ++w)
+                    if (w < W) L.dom[v * W + w] = d[w];
+                atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+                C.bytes += 4ull * W;
+                emp |= any == 0;
+            }
+        }
+        if (sft) {
+            uint32_t e[WM];
+            shl_w(d, sft, e);
+#pragma unroll
+            for (int w = 0; w < WM; ++w) Un[w] |= e[w];
+        } else {
+#pragma unroll
+            for (int w = 0; w < WM; ++w) Un[w] |= d[w];
+        }
+    }
+    int unpop = 0;
+#pragma unroll
+    for (int w = 0; w < WM; ++w)
+        if (w < W) unpop += __popc(wave_or(Un[w]));
+    const bool fail = (__ballot(emp) != 0) || unpop < k;
+    wsync();
+    return fail;
+}
+
+DEV long long floor_div(long long a, long long b) {  // b > 0
+    long long q = a / b;
+    if ((a % b != 0) && (a < 0)) --q;
+    return q;
+}
+
+// sum a_t x_t <= b (a_t > 0): S = sum a_t * min(D_t); fail if S > b; each
+// variable keeps the values v with a_t * v + (S - a_t * min(D_t)) <= b.
+template <int WM>
+DEV bool revise_linear(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt, Counters &C, int lane) {
+    const int W = I.W, k = g.k;
+    const int32_t *sc = I.gscope + g.scope_off;
+    const int64_t *co = I.gcoef + g.coef_off;
+    const long long b = co[0];
+    long long part = 0;
+    for (int t = lane; t < k; t += 64) {
+        const int v = sc[t];
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        part += (long long)co[1 + t] * (long long)(I.lo[v] + low_w(d, W));
+    }
+    const long long S = wave_sum64(part);
+    C.rev += lane == 0 ? 1 : 0;
+    C.bytes += lane == 0 ? 4ull * (u64)k * W : 0ull;
+    if (S > b) return true;
+    for (int t = lane; t < k; t += 64) {
+        const int v = sc[t];
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        const long long at = co[1 + t];
+        const long long mn = (long long)I.lo[v] + low_w(d, W);
+        const long long rest = S - at * mn;
+        const long long ubv = floor_div(b - rest, at);
+        const long long ubi = ubv - I.lo[v];
+        if (ubi < 32LL * W - 1) {
+            const int ub = (int)ubi;  // >= the min index, since S <= b
+            bool ch = false;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (w < W) {
+                    uint32_t nd = d[w] & mask_le(ub, w);
+                    ch |= nd != d[w];
+                    d[w] = nd;
+                }
+            }
+            if (ch) {
+#pragma unroll
+                for (int w = 0; w < WM; ++w)
+                    if (w < W) L.dom[v * W + w] = d[w];
+                atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+                C.bytes += 4ull * W;
+            }
+        }
+    }
+    wsync();
+    return false;
+}
+
+// ------------------------------------------------------------ propagate
+
+// Revise to the fixpoint.  L.dA holds the initially dirty variables.
+// Returns true on failure (wave-uniform).
+template <int WM>
+DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int lane) {
+    const int n = I.n;
+    const int ndw = (n + 63) >> 6, ngw = (I.n_glob + 63) >> 6;
+    const bool seg = layout == 2 && I.seg_ok;
+    const int sh = seg ? (31 - __clz(I.S)) : 0;
+    const int CH = seg ? (64 >> sh) : 64;
+    const int slot = seg ? (lane >> sh) : lane;
+    u64 *cur = L.dA, *nxt = L.dB;
+    for (;;) {
+        for (int w = lane; w < ndw; w += 64) nxt[w] = 0ull;
+        for (int w = lane; w < ngw; w += 64) L.gp[w] = 0ull;
+        wsync();
+        bool fail = false;
+        int cnt = 0, my_u = -1;
+        for (int w = 0; w < ndw && !fail; ++w) {
+            u64 bits = uni64(cur[w]);
+            while (bits && !fail) {
+                const int j = w * 64 + __ffsll((long long)bits) - 1;
+                bits &= bits - 1;
+                int beg = I.trig_off[j];
+                const int end = I.trig_off[j + 1];
+                while (beg < end) {
+                    const int take = min(end - beg, CH - cnt);
+                    if (slot >= cnt && slot < cnt + take) my_u = beg + slot - cnt;
+                    cnt += take;
+                    beg += take;
+                    if (cnt == CH) {
+                        fail = seg ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
+                                   : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+                        cnt = 0;
+                        my_u = -1;
+                        if (fail) break;
+                    }
+                }
+                if (I.n_glob) {
+                    const int gb = I.gtrig_off[j], ge = I.gtrig_off[j + 1];
+                    for (int t = gb + lane; t < ge; t += 64) {
+                        const int g = I.gtrig[t];
+                        atomicOr(&L.gp[g >> 6], 1ull << (g & 63));
+                    }
+                }
+            }
+        }
+        if (!fail && cnt > 0)
+            fail = seg ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane) : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+        if (fail) return true;
+        if (I.n_glob) {
+            wsync();
+            for (int w = 0; w < ngw; ++w) {
+                u64 bits = uni64(L.gp[w]);
+                while (bits) {
+                    const int gi = w * 64 + __ffsll((long long)bits) - 1;
+                    bits &= bits - 1;
+                    const GDesc g = I.gdesc[gi];
+                    const bool f = g.type == G_ALLDIFF ? revise_alldiff<WM>(I, g, L, nxt, C, lane)
+                                                       : revise_linear<WM>(I, g, L, nxt, C, lane);
+                    if (f) return true;
+                }
+            }
+        }
+        wsync();
+        bool anyn = false;
+        for (int w = lane; w < ndw; w += 64) anyn |= nxt[w] != 0ull;
+        if (__ballot(anyn) == 0ull) return false;
+        u64 *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+}
+
+// Mark every variable dirty (root propagation).
+DEV void dirty_all(const Lds &L, int n, int lane) {
+    const int ndw = (n + 63) >> 6;
+    for (int w = lane; w < ndw; w += 64) {
+        const int rem = n - 64 * w;
+        L.dA[w] = rem >= 64 ? ~0ull : ((1ull << rem) - 1ull);
+    }
+    wsync();
+}
+DEV void dirty_one(const Lds &L, int n, int x, int lane) {
+    const int ndw = (n + 63) >> 6;
+    for (int w = lane; w < ndw; w += 64) L.dA[w] = (w == (x >> 6)) ? (1ull << (x & 63)) : 0ull;
+    wsync();
+}
+
+// Node test: 0 open (returns the first-fail variable in *bx), 1 solution,
+// 2 failed (an empty domain).
+template <int WM>
+DEV int node_test(const InstDev &I, const Lds &L, int lane, int *bx) {
+    const int n = I.n, W = I.W;
+    uint32_t key = 0xFFFFFFFFu;
+    bool empty = false;
+    for (int i = lane; i < n; i += 64) {
+        int p = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k < W) p += __popc(L.dom[i * W + k]);
+        empty |= p == 0;
+        if (p >= 2) {
+            const uint32_t kk = ((uint32_t)p << 16) | (uint32_t)i;
+            key = kk < key ? kk : key;
+        }
+    }
+    if (__ballot(empty)) return 2;
+    key = wave_min(key);
+    if (key == 0xFFFFFFFFu) return 1;
+    *bx = (int)(key & 0xFFFFu);
+    return 0;
+}
+
+// ------------------------------------------------------------- queue
+
+// Bounded MPMC ring (per-cell sequence numbers).  Called by lane 0 only.
+DEV bool q_pop(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
+    uint32_t pos = ld_rlx(&P.q->head);
+    for (;;) {
+        const uint32_t c = pos & P.qmask;
+        const uint32_t s = ld_acq(&P.qseq[c]);
+        const int dif = (int)(s - (pos + 1u));
+        if (dif == 0) {
+            if (cas_u32(&P.q->head, &pos, pos + 1u)) {
+                *cell = c;
+                *posout = pos;
+                return true;
+            }
+        } else if (dif < 0) {
+            return false;
+        } else {
+            pos = ld_rlx(&P.q->head);
+        }
+    }
+}
+DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
+    uint32_t pos = ld_rlx(&P.q->tail);
+    for (;;) {
+        const uint32_t c = pos & P.qmask;
+        const uint32_t s = ld_acq(&P.qseq[c]);
+        const int dif = (int)(s - pos);
+        if (dif == 0) {
+            if (cas_u32(&P.q->tail, &pos, pos + 1u)) {
+                *cell = c;
+                *posout = pos;
+                return true;
+            }
+        } else if (dif < 0) {
+            return false;
+        } else {
+            pos = ld_rlx(&P.q->tail);
+        }
+    }
+}
+
+// Push a FRAME task (branch variable x with the remaining values vals over the
+// parent snapshot snap, which is nw words in LDS or global memory).
+template <int WM>
+DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uint32_t (&vals)[WM],
+                    const uint32_t *snap, int nw, int lane) {
+    uint32_t cell = 0, pos = 0;
+    int ok = 0;
+    if (lane == 0) {
+        add_i(&P.q->pending, 1);
+        ok = q_reserve(P, &cell, &pos) ? 1 : 0;
+        if (!ok) add_i(&P.q->pending, -1);
+    }
+    ok = uni(ok);
+    if (!ok) return false;
+    cell = uniu(cell);
+    pos = uniu(pos);
+    uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
+    if (lane == 0) {
+        s[0] = (uint32_t)inst;
+        s[1] = (uint32_t)K_FRAME;
+        s[2] = (uint32_t)x;
+        s[3] = (uint32_t)depth;
+    }
+    if (lane < WM) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k == lane) v = vals[k];
+        s[4 + lane] = v;
+    }
+    for (int t = lane; t < nw; t += 64) s[SLOT_HDR + t] = snap[t];
+    __threadfence();
+    if (lane == 0) st_rel(&P.qseq[cell], pos + 1u);
+    return true;
+}
+
+// ------------------------------------------------------------- worker
+
+template <int WM>
+struct Frame {  // cached top-of-trail frame
+    int x, depth;
+    uint32_t v[WM];
+};
+
+template <int WM>
+DEV void frame_store_meta(uint32_t *f, const Frame<WM> &F, int lane) {
+    if (lane == 0) {
+        f[0] = (uint32_t)F.x;
+        f[1] = (uint32_t)F.depth;
+    }
+    if (lane < WM) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k)
+            if (k == lane) v = F.v[k];
+        f[4 + lane] = v;
+    }
+}
+template <int WM>
+DEV void frame_load_meta(const uint32_t *f, Frame<WM> &F) {
+    F.x = uni((int)f[0]);
+    F.depth = uni((int)f[1]);
+#pragma unroll
+    for (int k = 0; k < WM; ++k) F.v[k] = uniu(f[4 + k]);
+}
+
+template <int WM>
+DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, const Lds &L,
+                         Counters &C, int lane) {
+    const int n = I.n, W = I.W;
+    if (P.mode == 0) {  // FIRST: one winner stores its assignment
+        int won = 0;
+        if (lane == 0) won = cas_i(&ctl->found, 0, 1) ? 1 : 0;
+        won = uni(won);
+        if (won) {
+            if (I.sol_buf && I.sol_cap > 0)
+                for (int i = lane; i < n; i += 64) {
+                    uint32_t d[WM];
+#pragma unroll
+                    for (int k = 0; k < WM; ++k) d[k] = k < W ? L.dom[i * W + k] : 0u;
+                    I.sol_buf[i] = I.lo[i] + low_w(d, W);
+                }
+            __threadfence();
+            if (lane == 0) {
+                add_u64(&ctl->count, 1ull);
+                ctl->reason = 1;
+                st_rel_i(&ctl->done, 1);
+            }
+        }
+        return;
+    }
+    const bool store = I.sol_buf && I.sol_cap > 0;
+    if (store || I.max_solutions) {
+        u64 slot = 0;
+        if (lane == 0) slot = add_u64(&ctl->n_slots, 1ull);
+        slot = uni64(slot);
+        if (store && slot < I.sol_cap) {
+            int32_t *row = I.sol_buf + slot * (u64)n;
+            for (int i = lane; i < n; i += 64) {
+                uint32_t d[WM];
+#pragma unroll
+                for (int k = 0; k < WM; ++k) d[k] = k < W ? L.dom[i * W + k] : 0u;
+                row[i] = I.lo[i] + low_w(d, W);
+            }
+        }
+        if (I.max_solutions && slot + 1 >= I.max_solutions && lane == 0) {
+            ctl->reason = 3;
+            st_rel_i(&ctl->done, 1);
+        }
+    } else {
+        C.sols += 1;
+    }
+}
+
+template <int WM>
+DEV void flush(InstCtl *ctl, Counters &C, int lane) {
+    const u64 rev = wave_sumu64(C.rev), bytes = wave_sumu64(C.bytes);
+    if (lane == 0) {
+        if (C.nodes) add_u64(&ctl->nodes, C.nodes);
+        if (C.fails) add_u64(&ctl->fails, C.fails);
+        if (C.sols) add_u64(&ctl->count, C.sols);
+        if (C.steals) add_u64(&ctl->steals, C.steals);
+        if (C.tasks) add_u64(&ctl->tasks, C.tasks);
+        if (rev) add_u64(&ctl->revisions, rev);
+        if (bytes) add_u64(&ctl->alg_bytes, bytes);
+    }
+    C.nodes = C.fails = C.sols = C.steals = C.tasks = 0;
+    C.rev = C.bytes = 0;
+}
+
+constexpr int POLL = 64;  // nodes between checks of stop flags and donation requests
+
+// Run one task to completion.
+template <int WM>
+DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
+                  Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
+                  long long t_start) {
+    const int n = I.n, W = I.W, nw = n * W;
+    const int layout = P.layout;
+    const uint32_t FW = P.frame_words;
+    int sp = 0;
+    Frame<WM> F;
+    bool have_open = false, need_restore = false;
+    int depth = F0.depth;
+    int since_poll = 0;
+    int open_x = 0;
+
+    if (kind == K_ROOT) {
+        // unary constraints restrict the root domains
+        for (int t = lane; t < I.n_unary; t += 64) {
+            const int v = I.unary[2 * t], off = I.unary[2 * t + 1];
+            for (int k = 0; k < W; ++k) atomicAnd(&L.dom[v * W + k], I.rows[off + k]);
+        }
+        wsync();
+        C.nodes += 1;
+        int bx = 0;
+        int st = node_test<WM>(I, L, lane, &bx);
+        if (st == 2) { C.fails += 1; return; }
+        dirty_all(L, n, lane);
+        if (propagate<WM>(I, L, layout, C, lane)) { C.fails += 1; return; }
+        st = node_test<WM>(I, L, lane, &bx);
+        if (st == 1) { record_solution<WM>(P, I, ctl, L, C, lane); return; }
+        have_open = true;
+        open_x = bx;
+        depth = 0;
+    } else {
+        // FRAME task: the snapshot is in L.dom; it becomes trail frame 0
+        F = F0;
+        for (int t = lane; t < nw; t += 64) trail[FRAME_HDR + t] = L.dom[t];
+        frame_store_meta<WM>(trail, F, lane);
+        sp = 1;
+        need_restore = false;
+    }
+
+    for (;;) {
+        if (have_open) {
+            have_open = false;
+            const int x = open_x;
+            // eager split: hand every child to the queue while the split target is unmet
+            bool split = false;
+            if (P.split_target > 0) {
+                long long prod = 0;
+                if (lane == 0) prod = (long long)ld_rlx_u64(&P.q->produced);
+                prod = unill(prod);
+                if (prod < P.split_target) split = true;
+            }
+            uint32_t dx[WM];
+#pragma unroll
+            for (int k = 0; k < WM; ++k) dx[k] = k < W ? uniu(L.dom[x * W + k]) : 0u;
+            if (split) {
+                // one FRAME task per value of x, each over this node's domains
+                uint32_t rem[WM];
+#pragma unroll
+                for (int k = 0; k < WM; ++k) rem[k] = dx[k];
+                int pushed = 0;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) {
+                    while (rem[k]) {
+                        const uint32_t lowb = rem[k] & (0u - rem[k]);
+                        uint32_t one[WM];
+#pragma unroll
+                        for (int q = 0; q < WM; ++q) one[q] = q == k ? lowb : 0u;
+                        if (!push_frame<WM>(P, b, x, depth, one, L.dom, nw, lane)) break;
+                        rem[k] &= ~lowb;
+                        ++pushed;
+                    }
+                }
+                if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
+                bool left = false;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) left |= rem[k] != 0u;
+                if (!left) goto next_child;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) dx[k] = rem[k];
+            }
+            // push a trail frame: snapshot of this node, branch variable x
+            {
+                uint32_t *f = trail + (size_t)sp * FW;
+                for (int t = lane; t < nw; t += 64) f[FRAME_HDR + t] = L.dom[t];
+                C.bytes += lane == 0 ? 4ull * nw : 0ull;
+                F.x = x;
+                F.depth = depth;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) F.v[k] = dx[k];
+                frame_store_meta<WM>(f, F, lane);
+                ++sp;
+                need_restore = false;
+            }
+        }
+    next_child:
+        // take the next value of the top frame, popping exhausted frames
+        for (;;) {
+            if (sp == 0) return;
+            bool emptyv = true;
+#pragma unroll
+            for (int k = 0; k < WM; ++k) emptyv &= F.v[k] == 0u;
+            if (emptyv) {
+                --sp;
+                if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
+                need_restore = true;
+                continue;
+            }
+            break;
+        }
+        {
+            int vi = -1;
+#pragma unroll
+            for (int k = WM - 1; k >= 0; --k)
+                if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
+#pragma unroll
+            for (int k = 0; k < WM; ++k) F.v[k] &= ~bit_in_word(vi, k);
+            uint32_t *f = trail + (size_t)(sp - 1) * FW;
+            if (lane < WM) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int k = 0; k < WM; ++k)
+                    if (k == lane) v = F.v[k];
+                f[4 + lane] = v;
+            }
+            if (need_restore) {
+                for (int t = lane; t < nw; t += 64) L.dom[t] = f[FRAME_HDR + t];
+                C.bytes += lane == 0 ? 4ull * nw : 0ull;
+                wsync();
+            }
+            need_restore = true;
+            if (lane < W) L.dom[F.x * W + lane] = bit_in_word(vi, lane);
+            depth = F.depth + 1;
+            dirty_one(L, n, F.x, lane);
+        }
+        C.nodes += 1;
+        {
+            const bool failed = propagate<WM>(I, L, layout, C, lane);
+            if (failed) {
+                C.fails += 1;
+            } else {
+                int bx = 0;
+                const int st = node_test<WM>(I, L, lane, &bx);
+                if (st == 1) {
+                    record_solution<WM>(P, I, ctl, L, C, lane);
+                    if (P.mode == 0) return;  // first mode: one solution ends the instance
+                } else {
+                    have_open = true;
+                    open_x = bx;
+                }
+            }
+        }
+        // periodic checks: stop flags, limits, donation
+        if (++since_poll >= POLL) {
+            since_poll = 0;
+            int stop = 0, idle = 0;
+            u64 qlen = 0;
+            if (lane == 0) {
+                stop = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
+                if (P.donate) {
+                    idle = ld_rlx_i(&P.q->idle);
+                    qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
+                }
+            }
+            stop = uni(stop);
+            if (stop) return;
+            if (I.max_nodes) {
+                u64 tot = 0;
+                if (lane == 0) tot = add_u64(&ctl->nodes, C.nodes) + C.nodes;
+                tot = uni64(tot);
+                C.nodes = 0;
+                if (tot >= I.max_nodes) {
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); }
+                    return;
+                }
+            }
+            if (P.time_ticks || P.cancel) {
+                int st2 = 0;
+                if (lane == 0) {
+                    if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
+                    if (P.cancel && *P.cancel) st2 = 3;
+                    if (st2) { P.q->stop_reason = st2; st_rel_i(&P.q->stop, 1); }
+                }
+                if (uni(st2)) return;
+            }
+            idle = uni(idle);
+            if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
+                // donate the shallowest frame that still has untried values
+                int tsel = -1;
+                for (int base = 0; base < sp && tsel < 0; base += 64) {
+                    const int t = base + lane;
+                    bool nz = false;
+                    if (t < sp) {
+                        const uint32_t *f = trail + (size_t)t * FW;
+                        for (int k = 0; k < W; ++k) nz |= f[4 + k] != 0u;
+                    }
+                    const u64 m = __ballot(nz);
+                    if (m) tsel = base + __ffsll((long long)m) - 1;
+                }
+                if (tsel >= 0) {
+                    uint32_t *f = trail + (size_t)tsel * FW;
+                    Frame<WM> D;
+                    frame_load_meta<WM>(f, D);
+                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, nw, lane)) {
+                        if (lane < WM) f[4 + lane] = 0u;
+                        if (tsel == sp - 1) {
+#pragma unroll
+                            for (int k = 0; k < WM; ++k) F.v[k] = 0u;
+                        }
+                        C.steals += 1;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int WM>
+__global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
+    extern __shared__ uint32_t lds_raw[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x >> 6;
+    const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
+    if (wid >= P.nworkers) return;
+    uint32_t *base = lds_raw + (size_t)wave * P.lds_words;
+    Lds L;
+    const int ndw = (P.nmax + 63) >> 6, ngw = (P.gmax + 63) >> 6;
+    int off = 0;
+    L.dom = base;
+    off += ((P.nmax * P.wmax) + 1) & ~1;
+    L.dA = (u64 *)(base + off);
+    off += 2 * ndw;
+    L.dB = (u64 *)(base + off);
+    off += 2 * ndw;
+    L.gp = (u64 *)(base + off);
+    off += 2 * (ngw > 0 ? ngw : 1);
+    L.scr = base + off;
+    uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
+    const long long t_start = (long long)wall_clock64();
+    Counters C = {0, 0, 0, 0, 0, 0, 0};
+    bool idle = false;
+    int backoff = 1;
+    for (;;) {
+        uint32_t cell = 0, pos = 0;
+        int got = 0;
+        if (lane == 0) got = q_pop(P, &cell, &pos) ? 1 : 0;
+        got = uni(got);
+        if (!got) {
+            int pend = 0;
+            if (lane == 0) {
+                if (!idle) add_i(&P.q->idle, 1);
+                pend = ld_rlx_i(&P.q->pending);
+            }
+            idle = true;
+            if (uni(pend) == 0) break;
+            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(4);
+            backoff = backoff < 32 ? backoff * 2 : 32;
+            continue;
+        }
+        backoff = 1;
+        if (idle) {
+            if (lane == 0) add_i(&P.q->idle, -1);
+            idle = false;
+        }
+        cell = uniu(cell);
+        pos = uniu(pos);
+        const uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
+        const int b = uni((int)s[0]);
+        const int kind = uni((int)s[1]);
+        Frame<WM> F0;
+        F0.x = uni((int)s[2]);
+        F0.depth = uni((int)s[3]);
+#pragma unroll
+        for (int k = 0; k < WM; ++k) F0.v[k] = uniu(s[4 + k]);
+        const InstDev I = P.inst[b];
+        const int nw = I.n * I.W;
+        if (kind == K_ROOT) {
+            for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
+        } else {
+            for (int t = lane; t < nw; t += 64) L.dom[t] = s[SLOT_HDR + t];
+        }
+        wsync();
+        __threadfence();
+        if (lane == 0) st_rel(&P.qseq[cell], pos + P.qmask + 1u);
+        InstCtl *ctl = P.ctl + b;
+        int skip = 0;
+        if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
+        if (!uni(skip)) run_task<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+        C.tasks += 1;
+        flush<WM>(ctl, C, lane);
+        __threadfence();
+        if (lane == 0) add_i(&P.q->pending, -1);
+    }
+    if (lane == 0 && idle) add_i(&P.q->idle, -1);
+}
+
+// Reset the queue and seed it with one ROOT task per instance.
+__global__ void init_kernel(SearchParams P) {
+    const uint32_t cap = P.qmask + 1u;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t c = tid; c < cap; c += stride) {
+        if (c < (uint32_t)P.B) {
+            uint32_t *s = P.qdata + (size_t)c * P.slot_words;
+            s[0] = c;
+            s[1] = (uint32_t)K_ROOT;
+            s[2] = 0;
+            s[3] = 0;
+            for (int k = 0; k < 8 && 4 + k < SLOT_HDR; ++k) s[4 + k] = 0;
+            P.qseq[c] = c + 1u;
+        } else {
+            P.qseq[c] = c;
+        }
+    }
+    for (uint32_t b = tid; b < (uint32_t)P.B; b += stride) {
+        InstCtl z;
+        z.count = z.n_slots = z.nodes = z.fails = z.revisions = z.alg_bytes = z.steals = z.tasks = 0;
+        z.done = z.reason = z.found = z.pad = 0;
+        P.ctl[b] = z;
+    }
+    if (tid == 0) {
+        P.q->head = 0;
+        P.q->tail = (uint32_t)P.B;
+        P.q->pending = P.B;
+        P.q->idle = 0;
+        P.q->produced = 0;
+        P.q->stop = 0;
+        P.q->stop_reason = 0;
+    }
+}
+
+// Root fixpoint of one instance (one wave): writes the domains and the verdict.
+template <int WM>
+__global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsigned long long *revs) {
+    extern __shared__ uint32_t lds_raw[];
+    const int lane = lane_id();
+    const InstDev I = P.inst[0];
+    Lds L;
+    const int ndw = (P.nmax + 63) >> 6, ngw = (P.gmax + 63) >> 6;
+    int off = 0;
+    L.dom = lds_raw;
+    off += ((P.nmax * P.wmax) + 1) & ~1;
+    L.dA = (u64 *)(lds_raw + off);
+    off += 2 * ndw;
+    L.dB = (u64 *)(lds_raw + off);
+    off += 2 * ndw;
+    L.gp = (u64 *)(lds_raw + off);
+    off += 2 * (ngw > 0 ? ngw : 1);
+    L.scr = lds_raw + off;
+    const int n = I.n, W = I.W, nw = n * W;
+    for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
+    wsync();
+    for (int t = lane; t < I.n_unary; t += 64) {
+        const int v = I.unary[2 * t], o = I.unary[2 * t + 1];
+        for (int k = 0; k < W; ++k) atomicAnd(&L.dom[v * W + k], I.rows[o + k]);
+    }
+    wsync();
+    Counters C = {0, 0, 0, 0, 0, 0, 0};
+    int bx = 0;
+    bool fail = node_test<WM>(I, L, lane, &bx) == 2;
+    if (!fail) {
+        dirty_all(L, n, lane);
+        fail = propagate<WM>(I, L, P.layout, C, lane);
+    }
+    wsync();
+    for (int t = lane; t < nw; t += 64) out[t] = L.dom[t];
+    const u64 r = wave_sumu64(C.rev);
+    if (lane == 0) {
+        *failed = fail ? 1 : 0;
+        *revs = r;
+    }
+}
+
+// -------------------------------------------------- host-side launchers
+template <int WM>
+static hipError_t launch_search_t(const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(search_kernel<WM>, dim3(blocks), dim3(64 * wpb), lds, st, P);
+    return hipGetLastError();
+}
+template <int WM>
+static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *failed,
+                                unsigned long long *revs, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(root_kernel<WM>, dim3(1), dim3(64), lds, st, P, out, failed, revs);
+    return hipGetLastError();
+}
+template <int WM>
+static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM>, 64 * wpb, lds);
+}
+
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st) {
+    switch (wmax) {
+    case 1: return launch_search_t<1>(P, blocks, wpb, lds, st);
+    case 2: return launch_search_t<2>(P, blocks, wpb, lds, st);
+    case 4: return launch_search_t<4>(P, blocks, wpb, lds, st);
+    default: return launch_search_t<8>(P, blocks, wpb, lds, st);
+    }
+}
+hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
+                       unsigned long long *revs, size_t lds, hipStream_t st) {
+    switch (wmax) {
+    case 1: return launch_root_t<1>(P, out, failed, revs, lds, st);
+    case 2: return launch_root_t<2>(P, out, failed, revs, lds, st);
+    case 4: return launch_root_t<4>(P, out, failed, revs, lds, st);
+    default: return launch_root_t<8>(P, out, failed, revs, lds, st);
+    }
+}
+hipError_t launch_init(const SearchParams &P, hipStream_t st) {
+    hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds) {
+    switch (wmax) {
+    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds);
+    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds);
+    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds);
+    default: return occupancy_t<8>(blocks_per_cu, wpb, lds);
+    }
+}
+
+}  // namespace cubics

@@ -1,0 +1,272 @@
+"""Python binding of libcubics.so (ctypes).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch supplies device memory (solution buffers) and the stream.
+Names follow the C ABI in include/cubics.h: ``cubics_create`` ->
+:class:`Context`, ``cubics_load`` -> :meth:`Context.load`, ``cubics_solve`` ->
+:meth:`Context.solve`, ``cubics_solve_batch`` -> :meth:`Context.solve_batch`,
+``cubics_root`` -> :meth:`Context.root`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcubics.so")
+
+MODE_FIRST, MODE_ALL, MODE_COUNT = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_SEG = 0, 1, 2
+BRANCH_FIRST_FAIL, BRANCH_LEARNED = 0, 1
+VERDICTS = {0: "SAT", 1: "UNSAT", 2: "LIMIT", 3: "CANCELLED"}
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}
+
+
+class CubicsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Limits(ctypes.Structure):
+    _fields_ = [
+        ("max_nodes", ctypes.c_uint64), ("max_solutions", ctypes.c_uint64),
+        ("time_ms", ctypes.c_int64), ("branching", ctypes.c_int32), ("layout", ctypes.c_int32),
+        ("split_target", ctypes.c_int64), ("sol_buf", ctypes.c_void_p),
+        ("sol_capacity", ctypes.c_uint64), ("workers", ctypes.c_int32), ("donate", ctypes.c_int32),
+        ("policy", ctypes.c_void_p),
+    ]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("verdict", ctypes.c_int32), ("truncated", ctypes.c_int32),
+        ("count", ctypes.c_uint64), ("n_written", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
+        ("fails", ctypes.c_uint64), ("revisions", ctypes.c_uint64), ("steals", ctypes.c_uint64),
+        ("alg_bytes", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
+        ("ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+    ]
+
+
+@dataclass
+class Result:
+    verdict: str
+    count: int
+    n_written: int
+    nodes: int
+    fails: int
+    revisions: int
+    steals: int
+    alg_bytes: int
+    tasks: int
+    truncated: bool
+    ms: float
+    kernel_ms: float
+    solutions: np.ndarray | None = None
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libcubics.so; raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libcubics.so not built at {path}; run __graft_entry__.build()")
+    # Load torch first: its bundled HIP runtime (same soname libamdhip64.so.7)
+    # then serves libcubics too, so the process holds a single HIP runtime.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.cubics_last_error.restype = ctypes.c_char_p
+    lib.cubics_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+    lib.cubics_destroy.argtypes = [vp]
+    lib.cubics_destroy.restype = None
+    lib.cubics_set_stream.argtypes = [vp, vp]
+    lib.cubics_cancel.argtypes = [vp]
+    lib.cubics_cancel.restype = None
+    lib.cubics_load.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.cubics_free.argtypes = [vp]
+    lib.cubics_free.restype = None
+    lib.cubics_prob_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
+    lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
+    lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
+    lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
+    for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
+              "cubics_root", "cubics_solve", "cubics_solve_batch"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        msg = _lib.cubics_last_error().decode()
+        raise CubicsError(rc, msg)
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class Problem:
+    """A CSP loaded on the device (owns the device copy)."""
+
+    def __init__(self, ctx, handle, inst):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = inst.n
+        self.W_in = inst.W                  # words per row of the caller's bit rows
+        self.W = self.info()["W"]           # words per domain on the device (>= W_in)
+        self.lo = np.asarray(inst.lo, dtype=np.int32).copy()
+        self.dsize = np.asarray(inst.dsize, dtype=np.int32).copy()
+        self.name = getattr(inst, "name", "")
+
+    def info(self):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(_lib.cubics_prob_info(self.handle, *[ctypes.byref(x) for x in v]))
+        return {"n": v[0].value, "W": v[1].value, "n_units": v[2].value, "n_global": v[3].value}
+
+    def free(self):
+        if self.handle:
+            _lib.cubics_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Context:
+    """cubics_create on `device`, using torch's current stream on that device."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = load_library()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("cubics needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.cubics_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _lib.cubics_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def cancel(self):
+        _lib.cubics_cancel(self.handle)
+
+    # ---------------------------------------------------------------- load
+    def load(self, inst) -> Problem:
+        keep = dict(
+            lo=np.ascontiguousarray(inst.lo, dtype=np.int32),
+            dsize=np.ascontiguousarray(inst.dsize, dtype=np.int32),
+            type=np.ascontiguousarray(inst.type, dtype=np.int32),
+            arity=np.ascontiguousarray(inst.arity, dtype=np.int32),
+            var_off=np.ascontiguousarray(inst.var_off, dtype=np.int64),
+            vars=np.ascontiguousarray(inst.vars, dtype=np.int32),
+            par_off=np.ascontiguousarray(inst.par_off, dtype=np.int64),
+            params=np.ascontiguousarray(inst.params, dtype=np.int64),
+            tab_off=np.ascontiguousarray(inst.tab_off, dtype=np.int64),
+            tabs=np.ascontiguousarray(inst.tabs, dtype=np.uint32),
+        )
+        init = None if inst.init is None else np.ascontiguousarray(inst.init, dtype=np.uint32)
+        h = ctypes.c_void_p()
+        _check(_lib.cubics_load(
+            self.handle, inst.n, _ptr(keep["lo"]), _ptr(keep["dsize"]), _ptr(init), inst.m,
+            _ptr(keep["type"]), _ptr(keep["arity"]), _ptr(keep["var_off"]), _ptr(keep["vars"]),
+            _ptr(keep["par_off"]), _ptr(keep["params"]), _ptr(keep["tab_off"]), _ptr(keep["tabs"]),
+            ctypes.byref(h)))
+        return Problem(self, h, inst)
+
+    # ---------------------------------------------------------------- root
+    def root(self, prob: Problem, layout: int = LAYOUT_AUTO):
+        out = np.zeros((max(prob.n, 1), prob.W), dtype=np.uint32)
+        failed = ctypes.c_int32()
+        _check(_lib.cubics_root(prob.handle, layout, out.ctypes.data, ctypes.byref(failed)))
+        return bool(failed.value), out[:prob.n, :prob.W_in].copy()
+
+    # --------------------------------------------------------------- solve
+    def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
+                split_target, sol_capacity, workers, donate, policy):
+        torch = _torch()
+        L = Limits()
+        L.max_nodes = max_nodes
+        L.max_solutions = max_solutions
+        L.time_ms = time_ms
+        L.branching = branching
+        L.layout = layout
+        L.split_target = split_target
+        L.workers = workers
+        L.donate = 1 if donate else 0
+        L.policy = policy.handle if policy is not None else None
+        buf = None
+        if mode == MODE_FIRST and sol_capacity == 0:
+            sol_capacity = 1
+        if sol_capacity > 0 and prob.n > 0:
+            buf = torch.empty((sol_capacity, prob.n), dtype=torch.int32, device=self.torch_device)
+            L.sol_buf = buf.data_ptr()
+            L.sol_capacity = sol_capacity
+        return L, buf
+
+    @staticmethod
+    def _result(r: _Result, buf, n) -> Result:
+        sols = None
+        if buf is not None:
+            sols = buf[: int(r.n_written)].cpu().numpy()
+        elif n == 0 and r.count > 0:
+            sols = np.zeros((int(min(r.n_written, 1)), 0), dtype=np.int32)
+        return Result(VERDICTS.get(r.verdict, str(r.verdict)), int(r.count), int(r.n_written),
+                      int(r.nodes), int(r.fails), int(r.revisions), int(r.steals), int(r.alg_bytes),
+                      int(r.tasks), bool(r.truncated), float(r.ms), float(r.kernel_ms), sols)
+
+    def solve(self, prob: Problem, mode: int = MODE_COUNT, *, max_nodes: int = 0,
+              max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
+              layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
+              workers: int = 0, donate: bool = True, policy=None) -> Result:
+        L, buf = self._limits(prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
+                              split_target, sol_capacity, workers, donate, policy)
+        r = _Result()
+        _check(_lib.cubics_solve(prob.handle, mode, ctypes.byref(L), ctypes.byref(r)))
+        return self._result(r, buf, prob.n)
+
+    def solve_batch(self, probs, mode: int = MODE_FIRST, *, max_nodes: int = 0,
+                    max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
+                    layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
+                    workers: int = 0, donate: bool = True, policy=None):
+        B = len(probs)
+        arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
+        lims = (Limits * B)()
+        bufs = []
+        for b, p in enumerate(probs):
+            L, buf = self._limits(p, mode, max_nodes, max_solutions, time_ms, branching, layout,
+                                  split_target, sol_capacity, workers, donate, policy)
+            lims[b] = L
+            bufs.append(buf)
+        res = (_Result * B)()
+        _check(_lib.cubics_solve_batch(arr, B, mode, lims, res))
+        return [self._result(res[b], bufs[b], probs[b].n) for b in range(B)]
