@@ -96,6 +96,10 @@ typedef struct {
     int32_t workers;         /* persistent workers (wavefronts); 0 = fill the device */
     int32_t donate;          /* 1 = busy workers donate subtrees to idle ones (default) */
     const cubics_policy *policy; /* required when branching == LEARNED */
+    int32_t tables_in_lds;   /* single-instance solves: 0 = stage the packed constraint
+                                tables in LDS once per workgroup when they fit (default),
+                                2 = always read them from HBM */
+    int32_t reserved;
 } cubics_limits;
 
 typedef struct {

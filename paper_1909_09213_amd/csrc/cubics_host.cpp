@@ -18,11 +18,11 @@
 #include "cubics_internal.h"
 
 namespace cubics {
-hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st);
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st);
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds);
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl);
 }  // namespace cubics
 
 using namespace cubics;
@@ -395,6 +395,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     if (unary.empty()) { unary.push_back(0); unary.push_back(0); }
     const size_t o_un = pk.add(unary.data(), unary.size() * 4);
     const size_t o_ft = pk.add(feat.data(), feat.size() * 4);
+    pk.add(nullptr, 0, 16);
+    pk.bytes.resize((pk.bytes.size() + 15) / 16 * 16, 0);
 
     HIPCHK(hipSetDevice(ctx->device));
     void *blob = nullptr;
@@ -444,6 +446,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     I.gcoef = (const int64_t *)(b8 + o_gc);
     I.unary = (const int32_t *)(b8 + o_un);
     I.feat_static = (const float *)(b8 + o_ft);
+    I.blob = (const uint32_t *)blob;
+    I.blob_words = (uint32_t)((pk.bytes.size() + 15) / 16 * 4);
     char key[160];
     snprintf(key, sizeof key, "W%d_d%d_n%d_g%d_t%d", W, (dmax + 7) / 8 * 8, (n + 15) / 16 * 16,
              p->n_glob > 0, has_table ? 1 : 0);
@@ -549,16 +553,22 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const Geometry G = geometry(probs, B);
     const int layout = choose_layout(probs, B, L0.layout);
 
-    // ---- workers: fill the device with co-resident wavefronts
+    // ---- workers: fill the device with co-resident wavefronts.  A single
+    // instance whose packed tables fit is staged in LDS once per workgroup.
+    const size_t LDS_WG_MAX = 64 * 1024;
     int wpb = 4;
-    size_t lds = (size_t)G.lds_words * 4 * wpb;
-    while (wpb > 1 && lds > 64 * 1024) {
+    const size_t per_wave = (size_t)G.lds_words * 4;
+    const size_t tab_bytes = (B == 1) ? (size_t)probs[0]->dev.blob_words * 4 : 0;
+    bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + per_wave * wpb <= LDS_WG_MAX;
+    if (L0.tables_in_lds == 2) tl = false;
+    size_t lds = (tl ? tab_bytes : 0) + per_wave * wpb;
+    while (wpb > 1 && lds > LDS_WG_MAX) {
         wpb /= 2;
-        lds = (size_t)G.lds_words * 4 * wpb;
+        lds = (tl ? tab_bytes : 0) + per_wave * wpb;
     }
-    if (lds > 64 * 1024) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", lds);
+    if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
-    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds));
+    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl));
     if (bpc < 1) bpc = 1;
     int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
     const int blocks = (nworkers + wpb - 1) / wpb;
@@ -621,7 +631,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
 
     HIPCHK(launch_init(P, st));
     HIPCHK(hipEventRecord(ctx->ev0, st));
-    HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, st));
+    HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, tl, st));
     HIPCHK(hipEventRecord(ctx->ev1, st));
     std::vector<InstCtl> ctl(B);
     QCtl qh;

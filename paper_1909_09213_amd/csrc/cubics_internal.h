@@ -52,6 +52,9 @@ struct InstDev {
     const int64_t *gcoef;
     const int32_t *unary;        // [n_unary][2] {var, row word offset}
     const float *feat_static;    // [n][2] static features for the learned policy
+    const uint32_t *blob;        // start of the packed problem (all arrays above lie inside)
+    uint32_t blob_words;         // its size in 32-bit words
+    uint32_t pad0;
     // per-instance solve settings (written by the host for each solve)
     int32_t *sol_buf;
     uint64_t sol_cap;

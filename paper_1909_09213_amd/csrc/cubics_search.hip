@@ -93,13 +93,19 @@ DEV void st_rel_i(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV int add_i(int32_t *p, int v) {
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+DEV void st_rlx(uint32_t *p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// device-scope fences: acquire invalidates, release writes back this XCD's L2
+DEV void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+DEV void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 DEV u64 add_u64(u64 *p, u64 v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV bool cas_u32(uint32_t *p, uint32_t *expected, uint32_t desired) {
-    return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_ACQ_REL,
+    return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_RELAXED,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 DEV bool cas_i(int32_t *p, int expected, int desired) {
@@ -672,15 +678,22 @@ DEV int node_test(const InstDev &I, const Lds &L, int lane, int *bx) {
 
 // ------------------------------------------------------------- queue
 
-// Bounded MPMC ring (per-cell sequence numbers).  Called by lane 0 only.
+// Bounded MPMC ring (per-cell sequence numbers; Vyukov's bounded queue).
+// Called by lane 0 only.  Every poll uses relaxed loads, so idle workers never
+// invalidate caches; a successful pop or reserve is followed by one acquire
+// fence, and publishing is preceded by one release fence.
+DEV bool q_maybe_nonempty(const SearchParams &P) {
+    return ld_rlx(&P.q->tail) != ld_rlx(&P.q->head);
+}
 DEV bool q_pop(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
     uint32_t pos = ld_rlx(&P.q->head);
     for (;;) {
         const uint32_t c = pos & P.qmask;
-        const uint32_t s = ld_acq(&P.qseq[c]);
+        const uint32_t s = ld_rlx(&P.qseq[c]);
         const int dif = (int)(s - (pos + 1u));
         if (dif == 0) {
             if (cas_u32(&P.q->head, &pos, pos + 1u)) {
+                fence_acq();
                 *cell = c;
                 *posout = pos;
                 return true;
@@ -696,10 +709,11 @@ DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
     uint32_t pos = ld_rlx(&P.q->tail);
     for (;;) {
         const uint32_t c = pos & P.qmask;
-        const uint32_t s = ld_acq(&P.qseq[c]);
+        const uint32_t s = ld_rlx(&P.qseq[c]);
         const int dif = (int)(s - pos);
         if (dif == 0) {
             if (cas_u32(&P.q->tail, &pos, pos + 1u)) {
+                fence_acq();
                 *cell = c;
                 *posout = pos;
                 return true;
@@ -743,8 +757,8 @@ DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uin
         s[4 + lane] = v;
     }
     for (int t = lane; t < nw; t += 64) s[SLOT_HDR + t] = snap[t];
-    __threadfence();
-    if (lane == 0) st_rel(&P.qseq[cell], pos + 1u);
+    fence_rel();
+    if (lane == 0) st_rlx(&P.qseq[cell], pos + 1u);
     return true;
 }
 
@@ -794,7 +808,7 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
                     for (int k = 0; k < WM; ++k) d[k] = k < W ? L.dom[i * W + k] : 0u;
                     I.sol_buf[i] = I.lo[i] + low_w(d, W);
                 }
-            __threadfence();
+            fence_rel();
             if (lane == 0) {
                 add_u64(&ctl->count, 1ull);
                 ctl->reason = 1;
@@ -1063,14 +1077,50 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     }
 }
 
-template <int WM>
+// A copy of an instance descriptor whose array pointers point into `tab`, a
+// copy of the instance's packed blob (used to stage one instance in LDS).
+DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
+    InstDev I = g;
+    const char *b0 = (const char *)g.blob;
+    const char *t0 = (const char *)tab;
+    I.lo = (const int32_t *)(t0 + ((const char *)g.lo - b0));
+    I.dom0 = (const uint32_t *)(t0 + ((const char *)g.dom0 - b0));
+    I.trig_off = (const int32_t *)(t0 + ((const char *)g.trig_off - b0));
+    I.units = (const Unit *)(t0 + ((const char *)g.units - b0));
+    I.rows = (const uint32_t *)(t0 + ((const char *)g.rows - b0));
+    I.gtrig_off = (const int32_t *)(t0 + ((const char *)g.gtrig_off - b0));
+    I.gtrig = (const int32_t *)(t0 + ((const char *)g.gtrig - b0));
+    I.gdesc = (const GDesc *)(t0 + ((const char *)g.gdesc - b0));
+    I.gscope = (const int32_t *)(t0 + ((const char *)g.gscope - b0));
+    I.gcoef = (const int64_t *)(t0 + ((const char *)g.gcoef - b0));
+    I.unary = (const int32_t *)(t0 + ((const char *)g.unary - b0));
+    I.feat_static = (const float *)(t0 + ((const char *)g.feat_static - b0));
+    I.blob = tab;
+    return I;
+}
+
+// Persistent search kernel: every wavefront is a worker that pops tasks from
+// the global queue until no task is pending anywhere.  TL: a single-instance
+// solve whose packed tables are staged once per workgroup in LDS.
+template <int WM, bool TL>
 __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
+    uint32_t tab_words = 0;
+    InstDev IL;
+    if (TL) {
+        const InstDev G = P.inst[0];
+        tab_words = G.blob_words;
+        const uint4 *src = (const uint4 *)G.blob;
+        uint4 *dst = (uint4 *)lds_raw;
+        for (uint32_t t = threadIdx.x; t < tab_words / 4; t += blockDim.x) dst[t] = src[t];
+        __syncthreads();
+        IL = rebase(G, lds_raw);
+    }
     if (wid >= P.nworkers) return;
-    uint32_t *base = lds_raw + (size_t)wave * P.lds_words;
+    uint32_t *base = lds_raw + tab_words + (size_t)wave * P.lds_words;
     Lds L;
     const int ndw = (P.nmax + 63) >> 6, ngw = (P.gmax + 63) >> 6;
     int off = 0;
@@ -1091,7 +1141,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     for (;;) {
         uint32_t cell = 0, pos = 0;
         int got = 0;
-        if (lane == 0) got = q_pop(P, &cell, &pos) ? 1 : 0;
+        if (lane == 0 && q_maybe_nonempty(P)) got = q_pop(P, &cell, &pos) ? 1 : 0;
         got = uni(got);
         if (!got) {
             int pend = 0;
@@ -1101,8 +1151,8 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
             }
             idle = true;
             if (uni(pend) == 0) break;
-            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(4);
-            backoff = backoff < 32 ? backoff * 2 : 32;
+            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(8);
+            backoff = backoff < 16 ? backoff * 2 : 16;
             continue;
         }
         backoff = 1;
@@ -1120,7 +1170,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
         F0.depth = uni((int)s[3]);
 #pragma unroll
         for (int k = 0; k < WM; ++k) F0.v[k] = uniu(s[4 + k]);
-        const InstDev I = P.inst[b];
+        const InstDev I = TL ? IL : P.inst[b];
         const int nw = I.n * I.W;
         if (kind == K_ROOT) {
             for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
@@ -1128,15 +1178,14 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
             for (int t = lane; t < nw; t += 64) L.dom[t] = s[SLOT_HDR + t];
         }
         wsync();
-        __threadfence();
-        if (lane == 0) st_rel(&P.qseq[cell], pos + P.qmask + 1u);
+        // the slot's words are in LDS now: hand the cell back to producers
+        if (lane == 0) st_rlx(&P.qseq[cell], pos + P.qmask + 1u);
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
         if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
         if (!uni(skip)) run_task<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
-        __threadfence();
         if (lane == 0) add_i(&P.q->pending, -1);
     }
     if (lane == 0 && idle) add_i(&P.q->idle, -1);
@@ -1221,8 +1270,11 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
 
 // -------------------------------------------------- host-side launchers
 template <int WM>
-static hipError_t launch_search_t(const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL(search_kernel<WM>, dim3(blocks), dim3(64 * wpb), lds, st, P);
+static hipError_t launch_search_t(const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
+    if (tl)
+        hipLaunchKernelGGL((search_kernel<WM, true>), dim3(blocks), dim3(64 * wpb), lds, st, P);
+    else
+        hipLaunchKernelGGL((search_kernel<WM, false>), dim3(blocks), dim3(64 * wpb), lds, st, P);
     return hipGetLastError();
 }
 template <int WM>
@@ -1232,16 +1284,17 @@ static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *f
     return hipGetLastError();
 }
 template <int WM>
-static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM>, 64 * wpb, lds);
+static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds, bool tl) {
+    if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true>, 64 * wpb, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false>, 64 * wpb, lds);
 }
 
-hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, hipStream_t st) {
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
     switch (wmax) {
-    case 1: return launch_search_t<1>(P, blocks, wpb, lds, st);
-    case 2: return launch_search_t<2>(P, blocks, wpb, lds, st);
-    case 4: return launch_search_t<4>(P, blocks, wpb, lds, st);
-    default: return launch_search_t<8>(P, blocks, wpb, lds, st);
+    case 1: return launch_search_t<1>(P, blocks, wpb, lds, tl, st);
+    case 2: return launch_search_t<2>(P, blocks, wpb, lds, tl, st);
+    case 4: return launch_search_t<4>(P, blocks, wpb, lds, tl, st);
+    default: return launch_search_t<8>(P, blocks, wpb, lds, tl, st);
     }
 }
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
@@ -1257,12 +1310,12 @@ hipError_t launch_init(const SearchParams &P, hipStream_t st) {
     hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, P);
     return hipGetLastError();
 }
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds) {
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl) {
     switch (wmax) {
-    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds);
-    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds);
-    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds);
-    default: return occupancy_t<8>(blocks_per_cu, wpb, lds);
+    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds, tl);
+    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds, tl);
+    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds, tl);
+    default: return occupancy_t<8>(blocks_per_cu, wpb, lds, tl);
     }
 }
 

@@ -37,7 +37,7 @@ class Limits(ctypes.Structure):
         ("time_ms", ctypes.c_int64), ("branching", ctypes.c_int32), ("layout", ctypes.c_int32),
         ("split_target", ctypes.c_int64), ("sol_buf", ctypes.c_void_p),
         ("sol_capacity", ctypes.c_uint64), ("workers", ctypes.c_int32), ("donate", ctypes.c_int32),
-        ("policy", ctypes.c_void_p),
+        ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -212,7 +212,7 @@ class Context:
 
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                split_target, sol_capacity, workers, donate, policy):
+                split_target, sol_capacity, workers, donate, policy, tables_in_lds=0):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -224,6 +224,7 @@ class Context:
         L.workers = workers
         L.donate = 1 if donate else 0
         L.policy = policy.handle if policy is not None else None
+        L.tables_in_lds = tables_in_lds
         buf = None
         if mode == MODE_FIRST and sol_capacity == 0:
             sol_capacity = 1
@@ -247,9 +248,9 @@ class Context:
     def solve(self, prob: Problem, mode: int = MODE_COUNT, *, max_nodes: int = 0,
               max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
               layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
-              workers: int = 0, donate: bool = True, policy=None) -> Result:
+              workers: int = 0, donate: bool = True, policy=None, tables_in_lds: int = 0) -> Result:
         L, buf = self._limits(prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                              split_target, sol_capacity, workers, donate, policy)
+                              split_target, sol_capacity, workers, donate, policy, tables_in_lds)
         r = _Result()
         _check(_lib.cubics_solve(prob.handle, mode, ctypes.byref(L), ctypes.byref(r)))
         return self._result(r, buf, prob.n)
