@@ -256,10 +256,11 @@ def global_family(index: int = 0, n: int = 200, lo: int = 0, d: int = 256, n_ad:
                   "lin_k": lin_k, "amax": amax, "b_pm": b_pm})
 
 
-def global_twin(index: int = 0) -> Instance:
-    """Scaled twin of the global family: 12 vars over 0..15, 2 all-different
-    over 6 vars, 3 linear <= over all vars (brute-forceable counts)."""
-    return global_family(index, n=12, lo=0, d=16, n_ad=2, k_ad=6, n_lin=3, lin_k=0,
+def global_twin(index: int = 0, n: int = 8, d: int = 8, k_ad: int = 5) -> Instance:
+    """Scaled twin of the global family: n vars over 0..d-1, 2 all-different
+    over k_ad vars, 3 linear <= over all vars with b = 45% of the maximum
+    sum (small enough to enumerate exhaustively at the default size)."""
+    return global_family(index, n=n, lo=0, d=d, n_ad=2, k_ad=k_ad, n_lin=3, lin_k=0,
                          amax=9, b_pm=450, base=SEED_GLOBAL + 100)
 
 

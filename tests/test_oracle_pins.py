@@ -504,3 +504,28 @@ def test_malformed_rejected():
     bad = _custom(2, [0, 0], [3, 3], [(6, (0, 1), (3, 1, 0), ())])
     with pytest.raises(ValueError):
         oracle.solve(bad)
+
+
+# ------------------------------------------------------ global-constraint twin
+
+@pytest.mark.parametrize("idx", range(3))
+def test_global_twin_vs_brute(idx):
+    """Scaled twin of the all-different + linear family: exhaustive count."""
+    inst = cspgen.global_twin(idx)
+    cnt, _ = oracle.brute(inst, limit=10 ** 8)
+    r = oracle.solve(inst, oracle.MODE_COUNT)
+    assert r.count == cnt and cnt > 0
+
+
+def test_rb_slices_partition_the_tree():
+    """Counting an instance whose root fixpoint keeps every value, in the
+    slices x0 = v, reproduces its count and its node count minus the root
+    (first-fail branches on x0 first when all domains are equal)."""
+    inst = cspgen.rb(7, n=14, d=6, dens_pm=350, tight_pm=300)
+    failed, bits, _ = oracle.root(inst)
+    assert not failed and all(int(b[0]) == 0b111111 for b in bits)
+    full = oracle.solve(inst, oracle.MODE_COUNT)
+    parts = [oracle.solve(inst.fix({0: v}), oracle.MODE_COUNT) for v in range(6)]
+    assert sum(p.count for p in parts) == full.count
+    assert sum(p.nodes for p in parts) == full.nodes - 1
+    assert sum(p.fails for p in parts) == full.fails
