@@ -99,6 +99,15 @@ typedef struct {
     int32_t tables_in_lds;   /* single-instance solves: 0 = stage the packed constraint
                                 tables in LDS once per workgroup when they fit (default),
                                 2 = always read them from HBM */
+    int32_t explore_pm;      /* trace collection: per-mille of branchings that pick uniformly
+                                among the 4 candidates with the smallest domains */
+    float *trace_buf;        /* device, caller-owned [trace_capacity][8] floats, or NULL.
+                                Each completed subtree under a branching records the
+                                branching variable's 5 features, the depth, 0 and the label
+                                log2(1 + nodes below the branching).  Subtrees that were
+                                split or donated are not recorded. */
+    uint64_t trace_capacity;
+    uint32_t seed;           /* exploration seed */
     int32_t reserved;
 } cubics_limits;
 
@@ -115,6 +124,7 @@ typedef struct {
     uint64_t alg_bytes;  /* algorithmic domain/table/trail bytes of the revisions and
                             trail operations executed */
     uint64_t tasks;      /* work-queue tasks processed */
+    uint64_t traces;     /* trace records written by the launch (see trace_buf) */
     double ms;           /* host wall time of the call */
     double kernel_ms;    /* duration of the search kernel (HIP events on the stream) */
 } cubics_result;
@@ -195,6 +205,38 @@ int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits,
    same device; the work runs on the first problem's context stream. */
 int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
                        const cubics_limits *limits, cubics_result *results);
+
+/* -------------------------------------------------------- learned policy
+ * The branching network (variable ordering, used when branching == LEARNED):
+ * features f (5 per candidate variable) -> 64 ReLU units -> 1 output, the
+ * predicted log2(1 + size of the subtree below branching on the variable);
+ * the candidate with the smallest prediction is branched on (lowest index on
+ * ties).  theta (449 floats, host) = W1[64][5] (row = hidden unit), b1[64],
+ * w2[64], b2.  Weights are used in bf16 (round to nearest even) with fp32
+ * accumulation on the matrix cores; theta stays the fp32 master copy.  The
+ * policy never changes what propagation computes, only the search order. */
+
+/* Upload theta (copied) and zero the optimizer state. */
+int cubics_policy_create(cubics_ctx *ctx, const float *theta, cubics_policy **out);
+void cubics_policy_free(cubics_policy *policy);
+int cubics_policy_get(const cubics_policy *policy, float *theta);
+int cubics_policy_set(cubics_policy *policy, const float *theta);
+/* y_dev[s] = network output for row s of x_dev (device, fp32 rows of stride
+   ld >= 5 floats, features in columns 0..4 - trace records have ld = 8).
+   Inputs are rounded to bf16 as in the search kernel. */
+int cubics_mlp_forward(const cubics_policy *policy, const float *x_dev, int32_t ld, int64_t N, float *y_dev);
+/* Gradient of the mean squared error mean_s (y_s - t_s)^2 with respect to
+   theta (targets t_dev[s * ldt], device), written to grad_dev (device, 449
+   floats; NULL = internal) and the loss to loss_dev (device, 1 float; NULL =
+   internal).  The bf16 rounding of weights, inputs and activations counts as
+   the identity (straight-through). */
+int cubics_mlp_grad(const cubics_policy *policy, const float *x_dev, int32_t ld, const float *t_dev,
+                    int32_t ldt, int64_t N, float *grad_dev, float *loss_dev);
+/* One full-batch training step: gradient, Adam (beta1 0.9, beta2 0.999,
+   eps 1e-8, bias-corrected, step >= 1) on theta, re-rounding of the bf16
+   weights.  *loss_host (nullable) receives the loss before the step. */
+int cubics_mlp_train_step(cubics_policy *policy, const float *x_dev, int32_t ld, const float *t_dev,
+                          int32_t ldt, int64_t N, float lr, int32_t step, float *loss_host);
 
 #ifdef __cplusplus
 }

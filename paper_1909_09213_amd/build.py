@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libcubics.so")
-SOURCES = ["cubics_search.hip", "cubics_host.cpp", "cubics_policy.cpp"]
+SOURCES = ["cubics_search.hip", "cubics_mlp.hip", "cubics_host.cpp", "cubics_policy.cpp"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]

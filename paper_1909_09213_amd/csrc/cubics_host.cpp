@@ -49,6 +49,8 @@ static int fail(int code, const char *fmt, ...) {
 
 extern "C" const char *cubics_last_error(void) { return g_err.c_str(); }
 
+int cubics_set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
 // ------------------------------------------------------- device buffers
 struct DevBuf {
     void *p = nullptr;
@@ -78,7 +80,7 @@ struct cubics_ctx {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     int wall_khz = 100000;
-    DevBuf inst, ctl, q, qseq, qdata, trail, rootout;
+    DevBuf inst, ctl, q, qseq, qdata, trail, rootout, tracecnt;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
     std::map<std::string, int> tuned;  // shape bucket -> layout
@@ -93,6 +95,9 @@ struct cubics_prob {
     bool has_table = false;
     std::string bucket;
 };
+
+hipStream_t cubics_ctx_stream(const cubics_ctx *c) { return c->stream; }
+int cubics_ctx_device(const cubics_ctx *c) { return c->device; }
 
 // ----------------------------------------------------------------- context
 extern "C" int cubics_create(int32_t device, void *hip_stream, cubics_ctx **out) {
@@ -128,7 +133,7 @@ extern "C" void cubics_destroy(cubics_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     c->inst.release(); c->ctl.release(); c->q.release(); c->qseq.release();
-    c->qdata.release(); c->trail.release(); c->rootout.release();
+    c->qdata.release(); c->trail.release(); c->rootout.release(); c->tracecnt.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->cancel_host) (void)hipHostFree(c->cancel_host);
@@ -368,11 +373,13 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                 gtrig[fill[v]++] = (int32_t)g;
             }
     }
-    // ---- static features of the learned policy: degree/(n-1), mean tightness
-    std::vector<float> feat(2 * (size_t)std::max(n, 1), 0.f);
+    // ---- static features of the learned policy: degree/(n-1), mean
+    // tightness of the variable's constraints, 1/dsize
+    std::vector<float> feat(4 * (size_t)std::max(n, 1), 0.f);
     for (int i = 0; i < n; ++i) {
-        feat[2 * i] = n > 1 ? (float)deg[i] / (float)(n - 1) : 0.f;
-        feat[2 * i + 1] = deg[i] ? (float)(tight_sum[i] / deg[i]) : 0.f;
+        feat[4 * i] = n > 1 ? (float)deg[i] / (float)(n - 1) : 0.f;
+        feat[4 * i + 1] = deg[i] ? (float)(tight_sum[i] / deg[i]) : 0.f;
+        feat[4 * i + 2] = 1.f / (float)dsize[i];
     }
 
     // ---- pack and upload
@@ -501,7 +508,7 @@ Geometry geometry(cubics_prob *const *probs, int B) {
     g.wmax = wm <= 1 ? 1 : wm <= 2 ? 2 : wm <= 4 ? 4 : 8;
     const int ndw = (g.nmax + 63) / 64, ngw = std::max((g.gmax + 63) / 64, 1);
     int words = ((g.nmax * g.wmax) + 1) & ~1;
-    words += 2 * ndw + 2 * ndw + 2 * ngw + 32;
+    words += 2 * ndw + 2 * ndw + 2 * ngw + ((g.nmax + 1) & ~1) + 32;
     g.lds_words = (words + 1) & ~1;
     return g;
 }
@@ -627,6 +634,14 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     P.wmax = G.wmax;
     P.gmax = G.gmax;
     if (L0.policy) policy_fill(L0.policy, &P.policy);
+    if (L0.trace_buf && L0.trace_capacity > 0) {
+        if ((rc = ctx->tracecnt.ensure(64))) return rc;
+        P.trace_out = L0.trace_buf;
+        P.trace_count = (unsigned long long *)ctx->tracecnt.p;
+        P.trace_cap = L0.trace_capacity;
+        P.explore_pm = L0.explore_pm;
+        P.seed = L0.seed;
+    }
     __atomic_store_n(ctx->cancel_host, 0, __ATOMIC_RELEASE);
 
     HIPCHK(launch_init(P, st));
@@ -635,6 +650,8 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     HIPCHK(hipEventRecord(ctx->ev1, st));
     std::vector<InstCtl> ctl(B);
     QCtl qh;
+    unsigned long long ntraces = 0;
+    if (P.trace_out) HIPCHK(hipMemcpyAsync(&ntraces, ctx->tracecnt.p, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(ctl.data(), ctx->ctl.p, sizeof(InstCtl) * B, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&qh, ctx->q.p, sizeof(QCtl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -655,6 +672,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         r.tasks = c.tasks;
         r.ms = ms;
         r.kernel_ms = kms;
+        r.traces = std::min<unsigned long long>(ntraces, P.trace_cap);
         const bool stopped = qh.stop != 0;
         const int stop_verdict = qh.stop_reason == 3 ? CUBICS_CANCELLED : CUBICS_LIMIT;
         if (mode == CUBICS_MODE_FIRST) {

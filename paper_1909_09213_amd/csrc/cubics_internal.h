@@ -83,18 +83,20 @@ struct QCtl {
 
 // Queue slot / trail frame header layout (uint32 words).
 constexpr int SLOT_HDR = 16;   // [0] inst [1] kind [2] x [3] depth [4..12) vals
-constexpr int FRAME_HDR = 16;  // [0] x [1] depth [4..12) vals
+constexpr int FRAME_HDR = 32;  // [0] x [1] depth [2] flags [4..12) vals [16..21) features [24..26) node stamp
 
-// Learned policy (device).
-constexpr int POLICY_F = 8;    // features per variable (5 used, zero padded)
+// Learned policy (device).  Parameter vector theta (fp32 master copy):
+// W1[64][5] (hidden-major), b1[64], w2[64], b2 -> 449 values.
+constexpr int POLICY_F = 5;    // features per variable
 constexpr int POLICY_H = 64;   // hidden units
+constexpr int POLICY_NP = POLICY_H * POLICY_F + POLICY_H + POLICY_H + 1;
+constexpr int OFF_W1 = 0, OFF_B1 = POLICY_H * POLICY_F, OFF_W2 = OFF_B1 + POLICY_H, OFF_B2 = OFF_W2 + POLICY_H;
 
 struct PolicyDev {
-    const uint16_t *w1;  // [H][F] bf16 (row h = weights of hidden unit h)
-    const float *b1;     // [H]
-    const uint16_t *w2;  // [H] bf16
-    float b2;
-    int32_t F, H;
+    const uint16_t *w1;  // [64][16] bf16, inputs >= POLICY_F zero
+    const float *b1;     // [64] (inside theta)
+    const uint16_t *w2;  // [64] bf16
+    const float *b2;     // [1] (inside theta)
 };
 
 struct SearchParams {
@@ -120,11 +122,14 @@ struct SearchParams {
     int32_t lds_words;     // per worker
     int32_t nmax, wmax, gmax;
     PolicyDev policy;
-    float *trace_out;      // optional trace recording (learned policy training)
+    float *trace_out;      // optional trace records [trace_cap][8] (learned policy training)
     unsigned long long *trace_count;
-    long long trace_cap;
-    int32_t trace_stride;  // ε-exploration rate denominator (0 = off)
+    unsigned long long trace_cap;
+    int32_t explore_pm;    // per-mille of branchings that explore among the 4 smallest domains
     uint32_t seed;
 };
+
+// Trace record (8 floats): features f0..f4, depth, 0, label = log2(1 + nodes below).
+constexpr int TRACE_WORDS = 8;
 
 }  // namespace cubics

@@ -30,6 +30,7 @@
 #include <stdint.h>
 
 #include "cubics_internal.h"
+#include "cubics_mlp.h"
 
 namespace cubics {
 
@@ -158,8 +159,9 @@ DEV uint32_t bit_in_word(int idx, int k) {  // word k of the singleton {idx}; id
 
 // ------------------------------------------------------------ counters
 struct Counters {
-    u64 nodes, fails, sols, steals, tasks;  // wave-uniform
-    u64 rev, bytes;                         // per lane
+    u64 nodes, fails, sols, steals, tasks;  // wave-uniform, flushed per instance
+    u64 rev, bytes;                         // per lane, flushed per instance
+    u64 stamp;                              // nodes of this worker, never reset
 };
 
 // ------------------------------------------------- binary unit revisions
@@ -272,6 +274,7 @@ struct Lds {
     uint32_t *dom;   // [nmax * wmax]
     u64 *dA, *dB;    // dirty sets [ndw]
     u64 *gp;         // pending globals [ngw]
+    uint32_t *fails; // [nmax] failures below each branching variable (policy feature)
     uint32_t *scr;   // 32 words scratch
 };
 
@@ -775,6 +778,7 @@ DEV void frame_store_meta(uint32_t *f, const Frame<WM> &F, int lane) {
     if (lane == 0) {
         f[0] = (uint32_t)F.x;
         f[1] = (uint32_t)F.depth;
+        f[2] = 0u;  // flags: bit 0 = part of the subtree left this worker
     }
     if (lane < WM) {
         uint32_t v = 0;
@@ -858,6 +862,113 @@ DEV void flush(InstCtl *ctl, Counters &C, int lane) {
 
 constexpr int POLL = 64;  // nodes between checks of stop flags and donation requests
 
+
+// ------------------------------------------------------ branching policy
+
+// Feature k (0..4) of variable i at a node of depth `depth`: domain fraction,
+// static degree / (n-1), mean static tightness, depth / n, log2(1 + fails).
+DEV float var_feature(const InstDev &I, const Lds &L, int i, int k, int depth, int pop) {
+    switch (k) {
+    case 0: return (float)pop * I.feat_static[4 * i + 2];
+    case 1: return I.feat_static[4 * i + 0];
+    case 2: return I.feat_static[4 * i + 1];
+    case 3: return (float)depth / (float)(I.n > 0 ? I.n : 1);
+    default: return log2f(1.f + (float)L.fails[i]);
+    }
+}
+
+template <int WM>
+DEV int var_pop(const InstDev &I, const Lds &L, int i) {
+    int p = 0;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if (k < I.W) p += __popc(L.dom[i * I.W + k]);
+    return p;
+}
+
+DEV u64 wave_min64(u64 v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const u64 w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+DEV u64 mix64(u64 z) {  // SplitMix64 finalizer (Steele, Lea and Flood 2014)
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Learned choice: the candidate (two or more values) with the smallest
+// predicted log-size of its subtree; lowest index on ties.  Candidates are
+// scored 16 at a time by the MFMA network.
+template <int WM>
+DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, int depth, int lane, int fallback) {
+    const int n = I.n;
+    const int row = lane & 15, kq = lane >> 4;
+    u64 best = ~0ull;
+    for (int base = 0; base < n; base += 16) {
+        const int i = base + row;
+        bf16x4 xT;
+        int pop = 0;
+        if (i < n) pop = var_pop<WM>(I, L, i);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * kq + j;
+            const float f = (i < n && k < POLICY_F) ? var_feature(I, L, i, k, depth, pop) : 0.f;
+            xT[j] = (short)f2bf(f);
+        }
+        const f32x4 acc = mlp_tile(P.policy, xT, lane, nullptr);
+        if (row == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ii = base + 4 * kq + r;
+                if (ii < n && var_pop<WM>(I, L, ii) >= 2) {
+                    const float y = acc[r] + *P.policy.b2;
+                    const uint32_t u = __float_as_uint(y);
+                    const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+                    const u64 key = ((u64)ord << 32) | (u64)ii;
+                    best = key < best ? key : best;
+                }
+            }
+        }
+    }
+    best = wave_min64(best);
+    return best == ~0ull ? fallback : (int)(best & 0xFFFFFFFFull);
+}
+
+// Exploration for trace collection: a uniform pick among the (up to) 4
+// candidates with the smallest domains (ties by index).
+template <int WM>
+DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
+    uint32_t keys[4];
+    int cnt = 0;
+    uint32_t prev = 0;
+    for (int q = 0; q < 4; ++q) {
+        uint32_t key = 0xFFFFFFFFu;
+        for (int i = lane; i < I.n; i += 64) {
+            const int p = var_pop<WM>(I, L, i);
+            if (p >= 2) {
+                const uint32_t kk = ((uint32_t)p << 16) | (uint32_t)i;
+                if ((q == 0 || kk > prev) && kk < key) key = kk;
+            }
+        }
+        key = wave_min(key);
+        if (key == 0xFFFFFFFFu) break;
+        keys[q] = key;
+        prev = key;
+        ++cnt;
+    }
+    const int pick = (int)(rnd % (u64)(cnt > 0 ? cnt : 1));
+    uint32_t kpick = keys[0];
+#pragma unroll
+    for (int q = 1; q < 4; ++q)
+        if (q == pick) kpick = keys[q];
+    return (int)(kpick & 0xFFFFu);
+}
+
 // Run one task to completion.
 template <int WM>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
@@ -872,6 +983,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     int depth = F0.depth;
     int since_poll = 0;
     int open_x = 0;
+    const bool tracing = P.trace_out != nullptr;
+    const bool learned = P.branching == 1;
+    if (tracing || learned) {
+        for (int i = lane; i < n; i += 64) L.fails[i] = 0u;
+        wsync();
+    }
 
     if (kind == K_ROOT) {
         // unary constraints restrict the root domains
@@ -881,6 +998,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         }
         wsync();
         C.nodes += 1;
+        C.stamp += 1;
         int bx = 0;
         int st = node_test<WM>(I, L, lane, &bx);
         if (st == 2) { C.fails += 1; return; }
@@ -903,7 +1021,13 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     for (;;) {
         if (have_open) {
             have_open = false;
-            const int x = open_x;
+            int x = open_x;
+            if (tracing && P.explore_pm > 0) {
+                const u64 rnd = mix64(((u64)P.seed << 40) ^ ((u64)(blockIdx.x * 16 + (threadIdx.x >> 6)) << 24) ^ C.stamp);
+                if ((int)(rnd % 1000ull) < P.explore_pm) x = choose_explore<WM>(I, L, lane, rnd >> 20);
+            } else if (learned) {
+                x = choose_learned<WM>(P, I, L, depth, lane, open_x);
+            }
             // eager split: hand every child to the queue while the split target is unmet
             bool split = false;
             if (P.split_target > 0) {
@@ -934,6 +1058,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                     }
                 }
                 if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
+                if (tracing && pushed)
+                    for (int t = lane; t < sp; t += 64) trail[(size_t)t * FW + 2] = 1u;
                 bool left = false;
 #pragma unroll
                 for (int k = 0; k < WM; ++k) left |= rem[k] != 0u;
@@ -951,6 +1077,14 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
 #pragma unroll
                 for (int k = 0; k < WM; ++k) F.v[k] = dx[k];
                 frame_store_meta<WM>(f, F, lane);
+                if (tracing) {
+                    const int px = var_pop<WM>(I, L, x);
+                    if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, L, x, lane, depth, px);
+                    if (lane == 0) {
+                        f[24] = (uint32_t)C.stamp;
+                        f[25] = (uint32_t)(C.stamp >> 32);
+                    }
+                }
                 ++sp;
                 need_restore = false;
             }
@@ -963,6 +1097,25 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
 #pragma unroll
             for (int k = 0; k < WM; ++k) emptyv &= F.v[k] == 0u;
             if (emptyv) {
+                if (tracing) {
+                    // the frame's subtree is complete: record (features, log2(1 + nodes below))
+                    const uint32_t *f = trail + (size_t)(sp - 1) * FW;
+                    const uint32_t flags = uniu(f[2]);
+                    const int fdepth = uni((int)f[1]);
+                    if (flags == 0u) {
+                        const u64 st0 = ((u64)uniu(f[25]) << 32) | uniu(f[24]);
+                        u64 idx = 0;
+                        if (lane == 0) idx = add_u64((u64 *)P.trace_count, 1ull);
+                        idx = uni64(idx);
+                        if (idx < P.trace_cap && lane < TRACE_WORDS) {
+                            float v = 0.f;
+                            if (lane < POLICY_F) v = ((const float *)f)[16 + lane];
+                            else if (lane == 5) v = (float)fdepth;
+                            else if (lane == 7) v = log2f(1.f + (float)(C.stamp - st0));
+                            P.trace_out[idx * TRACE_WORDS + lane] = v;
+                        }
+                    }
+                }
                 --sp;
                 if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
                 need_restore = true;
@@ -996,10 +1149,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             dirty_one(L, n, F.x, lane);
         }
         C.nodes += 1;
+        C.stamp += 1;
         {
             const bool failed = propagate<WM>(I, L, layout, C, lane);
             if (failed) {
                 C.fails += 1;
+                if ((tracing || learned) && lane == 0) L.fails[F.x] += 1u;
             } else {
                 int bx = 0;
                 const int st = node_test<WM>(I, L, lane, &bx);
@@ -1065,6 +1220,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                     frame_load_meta<WM>(f, D);
                     if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, nw, lane)) {
                         if (lane < WM) f[4 + lane] = 0u;
+                        if (tracing)
+                            for (int t = lane; t <= tsel; t += 64) trail[(size_t)t * FW + 2] = 1u;
                         if (tsel == sp - 1) {
 #pragma unroll
                             for (int k = 0; k < WM; ++k) F.v[k] = 0u;
@@ -1132,10 +1289,12 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     off += 2 * ndw;
     L.gp = (u64 *)(base + off);
     off += 2 * (ngw > 0 ? ngw : 1);
+    L.fails = base + off;
+    off += (P.nmax + 1) & ~1;
     L.scr = base + off;
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
     const long long t_start = (long long)wall_clock64();
-    Counters C = {0, 0, 0, 0, 0, 0, 0};
+    Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
     bool idle = false;
     int backoff = 1;
     for (;;) {
@@ -1215,6 +1374,7 @@ __global__ void init_kernel(SearchParams P) {
         z.done = z.reason = z.found = z.pad = 0;
         P.ctl[b] = z;
     }
+    if (tid == 0 && P.trace_count) *P.trace_count = 0ull;
     if (tid == 0) {
         P.q->head = 0;
         P.q->tail = (uint32_t)P.B;
@@ -1243,6 +1403,8 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
     off += 2 * ndw;
     L.gp = (u64 *)(lds_raw + off);
     off += 2 * (ngw > 0 ? ngw : 1);
+    L.fails = lds_raw + off;
+    off += (P.nmax + 1) & ~1;
     L.scr = lds_raw + off;
     const int n = I.n, W = I.W, nw = n * W;
     for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
@@ -1252,7 +1414,7 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
         for (int k = 0; k < W; ++k) atomicAnd(&L.dom[v * W + k], I.rows[o + k]);
     }
     wsync();
-    Counters C = {0, 0, 0, 0, 0, 0, 0};
+    Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
     int bx = 0;
     bool fail = node_test<WM>(I, L, lane, &bx) == 2;
     if (!fail) {

@@ -37,7 +37,9 @@ class Limits(ctypes.Structure):
         ("time_ms", ctypes.c_int64), ("branching", ctypes.c_int32), ("layout", ctypes.c_int32),
         ("split_target", ctypes.c_int64), ("sol_buf", ctypes.c_void_p),
         ("sol_capacity", ctypes.c_uint64), ("workers", ctypes.c_int32), ("donate", ctypes.c_int32),
-        ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("explore_pm", ctypes.c_int32),
+        ("trace_buf", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -46,7 +48,7 @@ class _Result(ctypes.Structure):
         ("verdict", ctypes.c_int32), ("truncated", ctypes.c_int32),
         ("count", ctypes.c_uint64), ("n_written", ctypes.c_uint64), ("nodes", ctypes.c_uint64),
         ("fails", ctypes.c_uint64), ("revisions", ctypes.c_uint64), ("steals", ctypes.c_uint64),
-        ("alg_bytes", ctypes.c_uint64), ("tasks", ctypes.c_uint64),
+        ("alg_bytes", ctypes.c_uint64), ("tasks", ctypes.c_uint64), ("traces", ctypes.c_uint64),
         ("ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
     ]
 
@@ -62,6 +64,7 @@ class Result:
     steals: int
     alg_bytes: int
     tasks: int
+    traces: int
     truncated: bool
     ms: float
     kernel_ms: float
@@ -97,8 +100,18 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
+    lib.cubics_policy_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
+    lib.cubics_policy_free.argtypes = [vp]
+    lib.cubics_policy_free.restype = None
+    lib.cubics_policy_get.argtypes = [vp, vp]
+    lib.cubics_policy_set.argtypes = [vp, vp]
+    lib.cubics_mlp_forward.argtypes = [vp, vp, i32, i64, vp]
+    lib.cubics_mlp_grad.argtypes = [vp, vp, i32, vp, i32, i64, vp, vp]
+    lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
-              "cubics_root", "cubics_solve", "cubics_solve_batch"):
+              "cubics_root", "cubics_solve", "cubics_solve_batch", "cubics_policy_create",
+              "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
+              "cubics_mlp_train_step"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -212,7 +225,8 @@ class Context:
 
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                split_target, sol_capacity, workers, donate, policy, tables_in_lds=0):
+                split_target, sol_capacity, workers, donate, policy, tables_in_lds=0,
+                trace=None, explore_pm=0, seed=0):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -225,6 +239,11 @@ class Context:
         L.donate = 1 if donate else 0
         L.policy = policy.handle if policy is not None else None
         L.tables_in_lds = tables_in_lds
+        if trace is not None:
+            L.trace_buf = trace.data_ptr()
+            L.trace_capacity = trace.shape[0]
+            L.explore_pm = explore_pm
+            L.seed = seed
         buf = None
         if mode == MODE_FIRST and sol_capacity == 0:
             sol_capacity = 1
@@ -243,7 +262,7 @@ class Context:
             sols = np.zeros((int(min(r.n_written, 1)), 0), dtype=np.int32)
         return Result(VERDICTS.get(r.verdict, str(r.verdict)), int(r.count), int(r.n_written),
                       int(r.nodes), int(r.fails), int(r.revisions), int(r.steals), int(r.alg_bytes),
-                      int(r.tasks), bool(r.truncated), float(r.ms), float(r.kernel_ms), sols)
+                      int(r.tasks), int(r.traces), bool(r.truncated), float(r.ms), float(r.kernel_ms), sols)
 
     def solve(self, prob: Problem, mode: int = MODE_COUNT, *, max_nodes: int = 0,
               max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
@@ -258,16 +277,83 @@ class Context:
     def solve_batch(self, probs, mode: int = MODE_FIRST, *, max_nodes: int = 0,
                     max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
-                    workers: int = 0, donate: bool = True, policy=None):
+                    workers: int = 0, donate: bool = True, policy=None, trace=None,
+                    explore_pm: int = 0, seed: int = 0):
+        """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()
         bufs = []
         for b, p in enumerate(probs):
             L, buf = self._limits(p, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                                  split_target, sol_capacity, workers, donate, policy)
+                                  split_target, sol_capacity, workers, donate, policy, 0,
+                                  trace if b == 0 else None, explore_pm, seed)
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()
         _check(_lib.cubics_solve_batch(arr, B, mode, lims, res))
         return [self._result(res[b], bufs[b], probs[b].n) for b in range(B)]
+
+
+class Policy:
+    """cubics_policy: the branching network's parameters on the device.
+
+    theta: 449 float32 values = W1[64][5], b1[64], w2[64], b2 (fp32 master)."""
+
+    NP = 449
+
+    def __init__(self, ctx: Context, theta):
+        self.ctx = ctx
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.shape == (self.NP,)
+        h = ctypes.c_void_p()
+        _check(_lib.cubics_policy_create(ctx.handle, th.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+
+    def get(self) -> np.ndarray:
+        out = np.zeros(self.NP, dtype=np.float32)
+        _check(_lib.cubics_policy_get(self.handle, out.ctypes.data))
+        return out
+
+    def set(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        _check(_lib.cubics_policy_set(self.handle, th.ctypes.data))
+
+    def forward(self, rec):
+        """rec: float32 cuda tensor [N, ld >= 5] (features in columns 0..4)."""
+        torch = _torch()
+        assert rec.dtype == torch.float32 and rec.is_contiguous()
+        N, ld = rec.shape
+        y = torch.empty(N, dtype=torch.float32, device=rec.device)
+        _check(_lib.cubics_mlp_forward(self.handle, rec.data_ptr(), ld, N, y.data_ptr()))
+        return y
+
+    def grad(self, rec, target_col: int = 7):
+        """Gradient of the MSE with targets rec[:, target_col] (trace records)."""
+        torch = _torch()
+        N, ld = rec.shape
+        g = torch.empty(self.NP, dtype=torch.float32, device=rec.device)
+        loss = torch.empty(1, dtype=torch.float32, device=rec.device)
+        _check(_lib.cubics_mlp_grad(self.handle, rec.data_ptr(), ld,
+                                    rec.data_ptr() + 4 * target_col, ld, N,
+                                    g.data_ptr(), loss.data_ptr()))
+        return g, loss
+
+    def train_step(self, rec, lr: float, step: int, target_col: int = 7) -> float:
+        N, ld = rec.shape
+        loss = ctypes.c_float()
+        _check(_lib.cubics_mlp_train_step(self.handle, rec.data_ptr(), ld,
+                                          rec.data_ptr() + 4 * target_col, ld, N, lr, step,
+                                          ctypes.byref(loss)))
+        return float(loss.value)
+
+    def close(self):
+        if self.handle:
+            _lib.cubics_policy_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,119 @@
+"""Learned branching on the GPU: forward, gradients and Adam of the policy
+network's kernels against the fp64 reference; the policy changes node counts
+but never verdicts, counts or solution sets."""
+import sys
+
+import numpy as np
+import pytest
+
+import cspgen
+import oracle
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cb():
+    from paper_1909_09213_amd import cubics
+    return cubics
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.Context(0)
+    yield c
+    c.close()
+
+
+def _rec(N, seed):
+    rng = np.random.default_rng(seed)
+    rec = np.zeros((N, 8), dtype=np.float32)
+    rec[:, 0] = rng.uniform(0, 1, N)
+    rec[:, 1] = rng.uniform(0, 0.5, N)
+    rec[:, 2] = rng.uniform(0, 0.6, N)
+    rec[:, 3] = rng.uniform(0, 1, N)
+    rec[:, 4] = np.log2(1 + rng.integers(0, 50, N))
+    rec[:, 7] = rng.uniform(0, 12, N)
+    return rec
+
+
+def test_forward_matches_reference(ctx, cb):
+    import torch
+    th = M.init_theta(3)
+    pol = cb.Policy(ctx, th)
+    rec = _rec(1000, 1)
+    y = pol.forward(torch.from_numpy(rec).to(ctx.torch_device)).cpu().numpy()
+    ref, _, _ = M.forward(th, rec[:, :5], quantized=True)
+    assert np.allclose(y, ref, rtol=2e-2, atol=1e-3), np.max(np.abs(y - ref))
+
+
+def test_gradient_matches_reference(ctx, cb):
+    import torch
+    th = M.init_theta(5)
+    pol = cb.Policy(ctx, th)
+    rec = _rec(3000, 2)
+    g, loss = pol.grad(torch.from_numpy(rec).to(ctx.torch_device))
+    g = g.cpu().numpy()
+    ref = M.grad(th, rec[:, :5], rec[:, 7], quantized=True)
+    scale = np.max(np.abs(ref))
+    assert np.all(np.abs(g - ref) <= 2e-2 * np.abs(ref) + 1e-3 * scale), np.max(np.abs(g - ref) / scale)
+    lref = M.loss(th, rec[:, :5], rec[:, 7], quantized=True)
+    assert abs(float(loss.item()) - lref) <= 2e-2 * lref
+
+
+def test_adam_step_matches_reference(ctx, cb):
+    import torch
+    th0 = M.init_theta(7)
+    pol = cb.Policy(ctx, th0)
+    rec = _rec(2000, 3)
+    X = torch.from_numpy(rec).to(ctx.torch_device)
+    lr = 1e-2
+    pol.train_step(X, lr, 1)
+    got = pol.get().astype(np.float64)
+    g = M.grad(th0, rec[:, :5], rec[:, 7], quantized=True)
+    want, _, _ = M.adam_step(th0.astype(np.float64), np.zeros(M.NP), np.zeros(M.NP), g, lr, 1)
+    # a first Adam step moves every parameter by lr * g / (|g| + eps): compare
+    # where the gradient is clearly non-zero, bound the move elsewhere
+    big = np.abs(g) > 1e-2 * np.max(np.abs(g))
+    assert np.allclose(got[big], want[big], rtol=0, atol=1e-4)
+    assert np.all(np.abs(got - th0) <= lr * (1 + 1e-3))
+
+
+def test_learned_policy_keeps_counts_and_verdicts(ctx, cb):
+    th = M.init_theta(11)
+    pol = cb.Policy(ctx, th)
+    insts = [cspgen.rb_sweep(i, base=123, nlo=12, nhi=22, dlo=5, dhi=10) for i in range(32)]
+    probs = [ctx.load(x) for x in insts]
+    ff = ctx.solve_batch(probs, cb.MODE_COUNT)
+    lr = ctx.solve_batch(probs, cb.MODE_COUNT, branching=cb.BRANCH_LEARNED, policy=pol)
+    differ = 0
+    for inst, a, b in zip(insts, ff, lr):
+        ref = oracle.solve(inst, oracle.MODE_COUNT)
+        assert a.count == b.count == ref.count, inst.name
+        differ += a.nodes != b.nodes
+    assert differ > 0  # the policy does change the search order
+    fa = ctx.solve_batch(probs, cb.MODE_FIRST)
+    fb = ctx.solve_batch(probs, cb.MODE_FIRST, branching=cb.BRANCH_LEARNED, policy=pol)
+    for inst, a, b in zip(insts, fa, fb):
+        assert a.verdict == b.verdict
+        if b.verdict == "SAT":
+            assert oracle.verify(inst, b.solutions[0])
+    # all-solutions sets under the policy equal the oracle's
+    q = cspgen.queens(7)
+    r = ctx.solve(ctx.load(q), cb.MODE_ALL, sol_capacity=64, branching=cb.BRANCH_LEARNED, policy=pol)
+    ref = oracle.solve(q, oracle.MODE_ALL, sol_cap=64)
+    assert sorted(map(tuple, r.solutions.tolist())) == sorted(map(tuple, ref.solutions.tolist()))
+
+
+def test_trace_collection_and_training(ctx, cb):
+    from paper_1909_09213_amd import learn
+    insts = learn.instances(base=cspgen.SEED_TRAIN, count=256)
+    rec = learn.collect(ctx, insts, cap=500000, explore_pm=250)
+    print(f"traces: {rec.shape[0]}", file=sys.stderr, flush=True)
+    assert rec.shape[0] > 1000
+    r = rec.cpu().numpy()
+    assert np.all(r[:, 7] >= 0) and np.all(np.isfinite(r))
+    assert np.all((r[:, 0] > 0) & (r[:, 0] <= 1))
+    pol, losses = learn.train(ctx, rec, steps=150, lr=1e-2)
+    assert losses[-1] < 0.7 * losses[0]
