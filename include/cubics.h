@@ -108,7 +108,9 @@ typedef struct {
                                 split or donated are not recorded. */
     uint64_t trace_capacity;
     uint32_t seed;           /* exploration seed */
-    int32_t reserved;
+    int32_t use_graph;       /* 1 = capture the launch sequence (queue reset + persistent
+                                search) in a hipGraph on first use and replay it on later
+                                calls with identical launch parameters */
 } cubics_limits;
 
 typedef struct {
@@ -205,6 +207,15 @@ int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits,
    same device; the work runs on the first problem's context stream. */
 int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
                        const cubics_limits *limits, cubics_result *results);
+
+/* Autotuner: run these problems for time_ms of search under each revision
+   layout (LANE: one lane per propagator; SEG: one lane per value of the
+   revised variable, ballot-assembled), measure search nodes per ms, and
+   remember the faster layout for the first problem's shape bucket (domain
+   words, domain size, variable count, constraint kinds).  Later solves with
+   layout AUTO on the same context use it.  *chosen (nullable) receives it. */
+int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
+                    int64_t time_ms, int32_t *chosen);
 
 /* -------------------------------------------------------- learned policy
  * The branching network (variable ordering, used when branching == LEARNED):

@@ -22,7 +22,7 @@ hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, s
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl);
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat);
 }  // namespace cubics
 
 using namespace cubics;
@@ -84,6 +84,7 @@ struct cubics_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
     std::map<std::string, int> tuned;  // shape bucket -> layout
+    std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
 };
 
 struct cubics_prob {
@@ -137,6 +138,7 @@ extern "C" void cubics_destroy(cubics_ctx *c) {
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->cancel_host) (void)hipHostFree(c->cancel_host);
+    for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     delete c;
 }
 
@@ -575,7 +577,8 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
-    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl));
+    const bool feat = L0.branching == CUBICS_BRANCH_LEARNED || (L0.trace_buf && L0.trace_capacity > 0);
+    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, feat));
     if (bpc < 1) bpc = 1;
     int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
     const int blocks = (nworkers + wpb - 1) / wpb;
@@ -644,10 +647,39 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     __atomic_store_n(ctx->cancel_host, 0, __ATOMIC_RELEASE);
 
-    HIPCHK(launch_init(P, st));
-    HIPCHK(hipEventRecord(ctx->ev0, st));
-    HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, tl, st));
-    HIPCHK(hipEventRecord(ctx->ev1, st));
+    if (L0.use_graph) {
+        // queue reset + persistent search as one captured graph, replayed for
+        // every later solve with identical launch parameters (the instance
+        // descriptors are re-uploaded above, outside the graph)
+        std::string key((const char *)&P, sizeof P);
+        const int dims[5] = {blocks, wpb, (int)lds, tl ? 1 : 0, G.wmax};
+        key.append((const char *)dims, sizeof dims);
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = launch_init(P, st);
+            hipError_t e2 = launch_search(G.wmax, P, blocks, wpb, lds, tl, st);
+            hipError_t e3 = hipStreamEndCapture(st, &graph);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(CUBICS_EDEVICE, "graph capture failed");
+            }
+            hipError_t e4 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e4 != hipSuccess) return fail(CUBICS_EDEVICE, "graph instantiation failed");
+            it = ctx->graphs.emplace(key, exec).first;
+        }
+        HIPCHK(hipEventRecord(ctx->ev0, st));
+        HIPCHK(hipGraphLaunch(it->second, st));
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+    } else {
+        HIPCHK(launch_init(P, st));
+        HIPCHK(hipEventRecord(ctx->ev0, st));
+        HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, tl, st));
+        HIPCHK(hipEventRecord(ctx->ev1, st));
+    }
     std::vector<InstCtl> ctl(B);
     QCtl qh;
     unsigned long long ntraces = 0;
@@ -704,6 +736,50 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
             r.count = count;
         }
     }
+    return CUBICS_OK;
+}
+
+extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
+                               int64_t time_ms, int32_t *chosen) {
+    if (!probs || B < 1 || !probs[0] || time_ms < 1) return fail(CUBICS_EINVAL, "bad autotune arguments");
+    bool seg_ok = true;
+    for (int b = 0; b < B; ++b) {
+        if (!probs[b]) return fail(CUBICS_EINVAL, "prob[%d] is NULL", b);
+        seg_ok &= probs[b]->dmax <= 64;
+    }
+    std::vector<cubics_limits> lim(B);
+    for (int b = 0; b < B; ++b) {
+        if (limits) lim[b] = limits[b];
+        else { memset(&lim[b], 0, sizeof(cubics_limits)); lim[b].donate = 1; }
+        lim[b].sol_buf = nullptr;
+        lim[b].sol_capacity = 0;
+        lim[b].trace_buf = nullptr;
+        lim[b].trace_capacity = 0;
+        lim[b].use_graph = 0;
+    }
+    lim[0].time_ms = time_ms;
+    std::vector<cubics_result> res(B);
+    int best = CUBICS_LAYOUT_LANE;
+    double best_rate = -1.0;
+    const int cands[2] = {CUBICS_LAYOUT_LANE, CUBICS_LAYOUT_SEG};
+    for (int ci = 0; ci < (seg_ok ? 2 : 1); ++ci) {
+        lim[0].layout = cands[ci];
+        // a warm-up run, then the timed one
+        for (int rep = 0; rep < 2; ++rep) {
+            int rc = solve_impl(probs, B, mode == CUBICS_MODE_FIRST ? CUBICS_MODE_FIRST : CUBICS_MODE_COUNT,
+                                lim.data(), res.data());
+            if (rc) return rc;
+        }
+        uint64_t nodes = 0;
+        for (int b = 0; b < B; ++b) nodes += res[b].nodes;
+        const double rate = (double)nodes / std::max(res[0].kernel_ms, 1e-3);
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = cands[ci];
+        }
+    }
+    probs[0]->ctx->tuned[probs[0]->bucket] = best;
+    if (chosen) *chosen = best;
     return CUBICS_OK;
 }
 

@@ -969,8 +969,9 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
     return (int)(kpick & 0xFFFFu);
 }
 
-// Run one task to completion.
-template <int WM>
+// Run one task to completion.  FEAT: the learned-policy / trace-recording
+// paths are compiled in (kept out of the plain kernel's register budget).
+template <int WM, bool FEAT>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
                   long long t_start) {
@@ -983,8 +984,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     int depth = F0.depth;
     int since_poll = 0;
     int open_x = 0;
-    const bool tracing = P.trace_out != nullptr;
-    const bool learned = P.branching == 1;
+    const bool tracing = FEAT && P.trace_out != nullptr;
+    const bool learned = FEAT && P.branching == 1;
     if (tracing || learned) {
         for (int i = lane; i < n; i += 64) L.fails[i] = 0u;
         wsync();
@@ -1259,7 +1260,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // Persistent search kernel: every wavefront is a worker that pops tasks from
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
-template <int WM, bool TL>
+template <int WM, bool TL, bool FEAT>
 __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     const int lane = lane_id();
@@ -1342,7 +1343,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
         if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
-        if (!uni(skip)) run_task<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+        if (!uni(skip)) run_task<WM, FEAT>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
         if (lane == 0) add_i(&P.q->pending, -1);
@@ -1431,13 +1432,19 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
 }
 
 // -------------------------------------------------- host-side launchers
+template <int WM, bool FEAT>
+static hipError_t launch_search_f(const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
+    if (tl)
+        hipLaunchKernelGGL((search_kernel<WM, true, FEAT>), dim3(blocks), dim3(64 * wpb), lds, st, P);
+    else
+        hipLaunchKernelGGL((search_kernel<WM, false, FEAT>), dim3(blocks), dim3(64 * wpb), lds, st, P);
+    return hipGetLastError();
+}
 template <int WM>
 static hipError_t launch_search_t(const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
-    if (tl)
-        hipLaunchKernelGGL((search_kernel<WM, true>), dim3(blocks), dim3(64 * wpb), lds, st, P);
-    else
-        hipLaunchKernelGGL((search_kernel<WM, false>), dim3(blocks), dim3(64 * wpb), lds, st, P);
-    return hipGetLastError();
+    const bool feat = P.trace_out != nullptr || P.branching == 1;
+    return feat ? launch_search_f<WM, true>(P, blocks, wpb, lds, tl, st)
+                : launch_search_f<WM, false>(P, blocks, wpb, lds, tl, st);
 }
 template <int WM>
 static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *failed,
@@ -1446,9 +1453,13 @@ static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *f
     return hipGetLastError();
 }
 template <int WM>
-static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds, bool tl) {
-    if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true>, 64 * wpb, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false>, 64 * wpb, lds);
+static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat) {
+    if (feat) {
+        if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true, true>, 64 * wpb, lds);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false, true>, 64 * wpb, lds);
+    }
+    if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true, false>, 64 * wpb, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false, false>, 64 * wpb, lds);
 }
 
 hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
@@ -1472,12 +1483,12 @@ hipError_t launch_init(const SearchParams &P, hipStream_t st) {
     hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, P);
     return hipGetLastError();
 }
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl) {
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat) {
     switch (wmax) {
-    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds, tl);
-    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds, tl);
-    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds, tl);
-    default: return occupancy_t<8>(blocks_per_cu, wpb, lds, tl);
+    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds, tl, feat);
+    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds, tl, feat);
+    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds, tl, feat);
+    default: return occupancy_t<8>(blocks_per_cu, wpb, lds, tl, feat);
     }
 }
 

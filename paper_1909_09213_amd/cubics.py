@@ -39,7 +39,7 @@ class Limits(ctypes.Structure):
         ("sol_capacity", ctypes.c_uint64), ("workers", ctypes.c_int32), ("donate", ctypes.c_int32),
         ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("explore_pm", ctypes.c_int32),
         ("trace_buf", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
     ]
 
 
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
+    lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32)]
     lib.cubics_policy_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.cubics_policy_free.argtypes = [vp]
     lib.cubics_policy_free.restype = None
@@ -109,7 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_mlp_grad.argtypes = [vp, vp, i32, vp, i32, i64, vp, vp]
     lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
-              "cubics_root", "cubics_solve", "cubics_solve_batch", "cubics_policy_create",
+              "cubics_root", "cubics_solve", "cubics_solve_batch", "cubics_autotune", "cubics_policy_create",
               "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
               "cubics_mlp_train_step"):
         getattr(lib, f).restype = ctypes.c_int
@@ -216,6 +217,22 @@ class Context:
             ctypes.byref(h)))
         return Problem(self, h, inst)
 
+    # ------------------------------------------------------------ autotune
+    def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, **kw) -> int:
+        """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG)."""
+        B = len(probs)
+        arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
+        lims = (Limits * B)()
+        for b in range(B):
+            L = Limits()
+            L.donate = 1 if kw.get("donate", True) else 0
+            L.split_target = kw.get("split_target", 0)
+            L.max_nodes = kw.get("max_nodes", 0)
+            lims[b] = L
+        chosen = ctypes.c_int32()
+        _check(_lib.cubics_autotune(arr, B, mode, lims, time_ms, ctypes.byref(chosen)))
+        return chosen.value
+
     # ---------------------------------------------------------------- root
     def root(self, prob: Problem, layout: int = LAYOUT_AUTO):
         out = np.zeros((max(prob.n, 1), prob.W), dtype=np.uint32)
@@ -226,7 +243,7 @@ class Context:
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                 split_target, sol_capacity, workers, donate, policy, tables_in_lds=0,
-                trace=None, explore_pm=0, seed=0):
+                trace=None, explore_pm=0, seed=0, use_graph=False):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -239,6 +256,7 @@ class Context:
         L.donate = 1 if donate else 0
         L.policy = policy.handle if policy is not None else None
         L.tables_in_lds = tables_in_lds
+        L.use_graph = 1 if use_graph else 0
         if trace is not None:
             L.trace_buf = trace.data_ptr()
             L.trace_capacity = trace.shape[0]
@@ -267,9 +285,11 @@ class Context:
     def solve(self, prob: Problem, mode: int = MODE_COUNT, *, max_nodes: int = 0,
               max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
               layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
-              workers: int = 0, donate: bool = True, policy=None, tables_in_lds: int = 0) -> Result:
+              workers: int = 0, donate: bool = True, policy=None, tables_in_lds: int = 0,
+              use_graph: bool = False) -> Result:
         L, buf = self._limits(prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                              split_target, sol_capacity, workers, donate, policy, tables_in_lds)
+                              split_target, sol_capacity, workers, donate, policy, tables_in_lds,
+                              use_graph=use_graph)
         r = _Result()
         _check(_lib.cubics_solve(prob.handle, mode, ctypes.byref(L), ctypes.byref(r)))
         return self._result(r, buf, prob.n)
@@ -278,7 +298,7 @@ class Context:
                     max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
-                    explore_pm: int = 0, seed: int = 0):
+                    explore_pm: int = 0, seed: int = 0, use_graph: bool = False):
         """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
@@ -287,7 +307,7 @@ class Context:
         for b, p in enumerate(probs):
             L, buf = self._limits(p, mode, max_nodes, max_solutions, time_ms, branching, layout,
                                   split_target, sol_capacity, workers, donate, policy, 0,
-                                  trace if b == 0 else None, explore_pm, seed)
+                                  trace if b == 0 else None, explore_pm, seed, use_graph)
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()

@@ -172,3 +172,27 @@ def test_errors(ctx, cb):
     bad.vars[1] = 0  # repeated scope variable
     with pytest.raises(cb.CubicsError):
         ctx.load(bad)
+
+
+def test_graph_replay_matches_eager(ctx, cb):
+    """The captured launch sequence, replayed with eager solves in between,
+    gives the eager result every time."""
+    inst = cspgen.queens(9)
+    ref = oracle.solve(inst, oracle.MODE_COUNT)
+    p = ctx.load(inst)
+    other = ctx.load(cspgen.queens(7))
+    for rep in range(4):
+        g = ctx.solve(p, cb.MODE_COUNT, use_graph=True)
+        assert (g.count, g.nodes, g.fails) == (ref.count, ref.nodes, ref.fails), rep
+        e = ctx.solve(other, cb.MODE_COUNT)
+        assert e.count == 40
+
+
+def test_autotune_then_auto_layout(ctx, cb):
+    inst = cspgen.rb(0).fix({0: 3, 1: 5, 2: 7})
+    p = ctx.load(inst)
+    chosen = ctx.autotune([p], cb.MODE_COUNT, time_ms=30)
+    assert chosen in (1, 2)
+    ref = oracle.solve(inst, oracle.MODE_COUNT)
+    r = ctx.solve(p, cb.MODE_COUNT)
+    assert (r.count, r.nodes) == (ref.count, ref.nodes)
