@@ -85,6 +85,7 @@ struct cubics_ctx {
     int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
     std::map<std::string, int> tuned;  // shape bucket -> layout
     std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
+    hipStream_t graph_stream = nullptr;  // capture stream when the caller's is the null stream
 };
 
 struct cubics_prob {
@@ -139,6 +140,7 @@ extern "C" void cubics_destroy(cubics_ctx *c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->cancel_host) (void)hipHostFree(c->cancel_host);
     for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (c->graph_stream) (void)hipStreamDestroy(c->graph_stream);
     delete c;
 }
 
@@ -559,6 +561,12 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     HIPCHK(hipSetDevice(ctx->device));
     hipStream_t st = ctx->stream;
+    if (L0.use_graph && st == nullptr) {
+        // the null stream cannot be captured: use a blocking stream of the
+        // context (it still orders with the null stream)
+        if (!ctx->graph_stream) HIPCHK(hipStreamCreate(&ctx->graph_stream));
+        st = ctx->graph_stream;
+    }
     const Geometry G = geometry(probs, B);
     const int layout = choose_layout(probs, B, L0.layout);
 
