@@ -101,13 +101,16 @@ def test_batch_first_small_vs_oracle(ctx, cb, layout):
 
 
 def test_batch_count_matches_single(ctx, cb):
-    insts = _sweep(16, nhi=24, dhi=10, base=99)
+    insts = _sweep(16, nlo=12, nhi=20, dlo=5, dhi=9, plo=350, phi=550, tlo=300, thi=450, base=99)
     probs = [ctx.load(x) for x in insts]
-    res = ctx.solve_batch(probs, cb.MODE_COUNT)
+    res = ctx.solve_batch(probs, cb.MODE_COUNT, max_nodes=50_000_000)
+    resolved = 0
     for inst, r in zip(insts, res):
-        ref = oracle.solve(inst, oracle.MODE_COUNT, max_nodes=2000000)
+        ref = oracle.solve(inst, oracle.MODE_COUNT, max_nodes=300000)
         if ref.verdict != "LIMIT":
+            resolved += 1
             assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails), inst.name
+    assert resolved >= 8
 
 
 def test_batch_full_size(ctx, cb):
@@ -115,7 +118,7 @@ def test_batch_full_size(ctx, cb):
     insts = _sweep(4096)
     _say("generated 4096 sweep instances")
     probs = [ctx.load(x) for x in insts]
-    res = ctx.solve_batch(probs, cb.MODE_FIRST, max_nodes=10 ** 7)
+    res = ctx.solve_batch(probs, cb.MODE_FIRST, max_nodes=2_000_000)
     n_sat = n_unsat = 0
     for inst, r in zip(insts, res):
         if r.verdict == "SAT":
