@@ -981,6 +981,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     int sp = 0;
     Frame<WM> F;
     bool have_open = false, need_restore = false;
+    // register copy of the top frame's snapshot (lane-per-word), so that the
+    // siblings under one frame are restored without an HBM round trip
+    constexpr int NC = WM <= 2 ? 4 : 1;
+    const bool cache_ok = WM <= 2 && nw <= 64 * NC;
+    uint32_t snapc[NC];
+    bool snap_valid = false;
     int depth = F0.depth;
     int since_poll = 0;
     int open_x = 0;
@@ -1014,6 +1020,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         // FRAME task: the snapshot is in L.dom; it becomes trail frame 0
         F = F0;
         for (int t = lane; t < nw; t += 64) trail[FRAME_HDR + t] = L.dom[t];
+        if (cache_ok) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (lane + 64 * c < nw) snapc[c] = L.dom[lane + 64 * c];
+            snap_valid = true;
+        }
         frame_store_meta<WM>(trail, F, lane);
         sp = 1;
         need_restore = false;
@@ -1070,8 +1082,22 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             }
             // push a trail frame: snapshot of this node, branch variable x
             {
+                if (sp > 0 && lane < WM) {
+                    // the outgoing top frame keeps its remaining values in HBM
+                    uint32_t v = 0;
+#pragma unroll
+                    for (int k = 0; k < WM; ++k)
+                        if (k == lane) v = F.v[k];
+                    trail[(size_t)(sp - 1) * FW + 4 + lane] = v;
+                }
                 uint32_t *f = trail + (size_t)sp * FW;
                 for (int t = lane; t < nw; t += 64) f[FRAME_HDR + t] = L.dom[t];
+                if (cache_ok) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (lane + 64 * c < nw) snapc[c] = L.dom[lane + 64 * c];
+                    snap_valid = true;
+                }
                 C.bytes += lane == 0 ? 4ull * nw : 0ull;
                 F.x = x;
                 F.depth = depth;
@@ -1120,6 +1146,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 --sp;
                 if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
                 need_restore = true;
+                snap_valid = false;
                 continue;
             }
             break;
@@ -1131,16 +1158,23 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
 #pragma unroll
             for (int k = 0; k < WM; ++k) F.v[k] &= ~bit_in_word(vi, k);
-            uint32_t *f = trail + (size_t)(sp - 1) * FW;
-            if (lane < WM) {
-                uint32_t v = 0;
-#pragma unroll
-                for (int k = 0; k < WM; ++k)
-                    if (k == lane) v = F.v[k];
-                f[4 + lane] = v;
-            }
+            const uint32_t *f = trail + (size_t)(sp - 1) * FW;
             if (need_restore) {
-                for (int t = lane; t < nw; t += 64) L.dom[t] = f[FRAME_HDR + t];
+                if (snap_valid) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (lane + 64 * c < nw) L.dom[lane + 64 * c] = snapc[c];
+                } else if (cache_ok) {
+#pragma unroll
+                    for (int c = 0; c < NC; ++c)
+                        if (lane + 64 * c < nw) {
+                            snapc[c] = f[FRAME_HDR + lane + 64 * c];
+                            L.dom[lane + 64 * c] = snapc[c];
+                        }
+                    snap_valid = true;
+                } else {
+                    for (int t = lane; t < nw; t += 64) L.dom[t] = f[FRAME_HDR + t];
+                }
                 C.bytes += lane == 0 ? 4ull * nw : 0ull;
                 wsync();
             }
@@ -1205,20 +1239,26 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
                 // donate the shallowest frame that still has untried values
                 int tsel = -1;
-                for (int base = 0; base < sp && tsel < 0; base += 64) {
+                // (frames below the top keep their values in HBM; the top's are in F)
+                bool topnz = false;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) topnz |= F.v[k] != 0u;
+                for (int base = 0; base < sp - 1 && tsel < 0; base += 64) {
                     const int t = base + lane;
                     bool nz = false;
-                    if (t < sp) {
+                    if (t < sp - 1) {
                         const uint32_t *f = trail + (size_t)t * FW;
                         for (int k = 0; k < W; ++k) nz |= f[4 + k] != 0u;
                     }
                     const u64 m = __ballot(nz);
                     if (m) tsel = base + __ffsll((long long)m) - 1;
                 }
+                if (tsel < 0 && topnz) tsel = sp - 1;
                 if (tsel >= 0) {
                     uint32_t *f = trail + (size_t)tsel * FW;
                     Frame<WM> D;
                     frame_load_meta<WM>(f, D);
+                    if (tsel == sp - 1) D = F;
                     if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, nw, lane)) {
                         if (lane < WM) f[4 + lane] = 0u;
                         if (tracing)

@@ -99,3 +99,58 @@ def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_node
     for p in probs:
         p.free()
     return out
+
+
+def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps: int = 300,
+               lr: float = 1e-2, explore_pm: int = 250, eval_max_nodes: int = 50_000_000,
+               train_base: int = cspgen.SEED_TRAIN, eval_base: int = cspgen.SEED_EVAL):
+    """Train on traces from n_train seeded instances, evaluate time-to-all
+    (count mode) on n_eval held-out seeds under first-fail and the policy.
+    Returns a report dict; raises if any verdict or count differs."""
+    t0 = time.perf_counter()
+    train_insts = instances(train_base, n_train)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rec = collect(ctx, train_insts, explore_pm=explore_pm)
+    t_collect = time.perf_counter() - t0
+    del train_insts
+    t0 = time.perf_counter()
+    pol, losses = train(ctx, rec, steps=steps, lr=lr)
+    t_train = time.perf_counter() - t0
+    eval_insts = instances(eval_base, n_eval)
+    ev = evaluate(ctx, eval_insts, pol, cb.MODE_COUNT, max_nodes=eval_max_nodes)
+    ff, le = ev["first_fail"]["results"], ev["learned"]["results"]
+    both = [i for i in range(n_eval) if ff[i].verdict != "LIMIT" and le[i].verdict != "LIMIT"]
+    for i in both:
+        if ff[i].count != le[i].count or ff[i].verdict != le[i].verdict:
+            raise AssertionError(f"policy changed the count of eval instance {i}")
+    nodes_ff = sum(ff[i].nodes for i in both)
+    nodes_le = sum(le[i].nodes for i in both)
+    report = {
+        "train_instances": n_train, "eval_instances": n_eval, "eval_resolved_by_both": len(both),
+        "trace_records": int(rec.shape[0]), "train_steps": steps,
+        "loss_first": losses[0], "loss_last": losses[-1],
+        "nodes_first_fail": nodes_ff, "nodes_learned": nodes_le,
+        "node_ratio_learned_over_ff": nodes_le / max(nodes_ff, 1),
+        "time_to_all_ms_first_fail": ev["first_fail"]["kernel_ms"],
+        "time_to_all_ms_learned": ev["learned"]["kernel_ms"],
+        "time_ratio_learned_over_ff": ev["learned"]["kernel_ms"] / max(ev["first_fail"]["kernel_ms"], 1e-9),
+        "seconds": {"generate": t_gen, "collect": t_collect, "train": t_train},
+        "theta": pol.get().tolist(),
+    }
+    return report
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--eval", type=int, default=4096)
+    ap.add_argument("--steps", type=int, default=300)
+    args = ap.parse_args()
+    ctx = cb.Context(0)
+    rep = experiment(ctx, n_train=args.train, n_eval=args.eval, steps=args.steps)
+    theta = rep.pop("theta")
+    print(json.dumps(rep))
