@@ -18,11 +18,13 @@
 #include "cubics_internal.h"
 
 namespace cubics {
-hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st);
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
+                         hipStream_t st);
+int search_variant(bool feat, bool glob, bool seg);
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat);
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant);
 }  // namespace cubics
 
 using namespace cubics;
@@ -586,7 +588,8 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
     const bool feat = L0.branching == CUBICS_BRANCH_LEARNED || (L0.trace_buf && L0.trace_capacity > 0);
-    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, feat));
+    const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG);
+    HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, variant));
     if (bpc < 1) bpc = 1;
     int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
     const int blocks = (nworkers + wpb - 1) / wpb;
@@ -668,7 +671,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
             hipGraphExec_t exec = nullptr;
             HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t e1 = launch_init(P, st);
-            hipError_t e2 = launch_search(G.wmax, P, blocks, wpb, lds, tl, st);
+            hipError_t e2 = launch_search(G.wmax, P, blocks, wpb, lds, tl, variant, st);
             hipError_t e3 = hipStreamEndCapture(st, &graph);
             if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -685,7 +688,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     } else {
         HIPCHK(launch_init(P, st));
         HIPCHK(hipEventRecord(ctx->ev0, st));
-        HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, tl, st));
+        HIPCHK(launch_search(G.wmax, P, blocks, wpb, lds, tl, variant, st));
         HIPCHK(hipEventRecord(ctx->ev1, st));
     }
     std::vector<InstCtl> ctl(B);

@@ -32,6 +32,13 @@
 #include "cubics_internal.h"
 #include "cubics_mlp.h"
 
+// This file is compiled once per domain width (CUBICS_ONLY_WM = 1, 2, 4, 8)
+// so that the kernel variants build in parallel; the width-1 object also
+// carries the queue-reset kernel and the dispatchers.
+#ifndef CUBICS_ONLY_WM
+#define CUBICS_ONLY_WM 1
+#endif
+
 namespace cubics {
 
 #define DEV __device__ __forceinline__
@@ -568,11 +575,12 @@ DEV bool revise_linear(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt,
 
 // Revise to the fixpoint.  L.dA holds the initially dirty variables.
 // Returns true on failure (wave-uniform).
-template <int WM>
+// GLOB: global constraints may occur; SEGC: the SEG layout is compiled in.
+template <int WM, bool GLOB, bool SEGC>
 DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int lane) {
     const int n = I.n;
     const int ndw = (n + 63) >> 6, ngw = (I.n_glob + 63) >> 6;
-    const bool seg = layout == 2 && I.seg_ok;
+    const bool seg = SEGC && layout == 2 && I.seg_ok;
     const int sh = seg ? (31 - __clz(I.S)) : 0;
     const int CH = seg ? (64 >> sh) : 64;
     const int slot = seg ? (lane >> sh) : lane;
@@ -596,14 +604,14 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
                     cnt += take;
                     beg += take;
                     if (cnt == CH) {
-                        fail = seg ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
-                                   : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+                        fail = (SEGC && seg) ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
+                                             : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
                         cnt = 0;
                         my_u = -1;
                         if (fail) break;
                     }
                 }
-                if (I.n_glob) {
+                if (GLOB && I.n_glob) {
                     const int gb = I.gtrig_off[j], ge = I.gtrig_off[j + 1];
                     for (int t = gb + lane; t < ge; t += 64) {
                         const int g = I.gtrig[t];
@@ -613,9 +621,10 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
             }
         }
         if (!fail && cnt > 0)
-            fail = seg ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane) : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+            fail = (SEGC && seg) ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
+                                 : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
         if (fail) return true;
-        if (I.n_glob) {
+        if (GLOB && I.n_glob) {
             wsync();
             for (int w = 0; w < ngw; ++w) {
                 u64 bits = uni64(L.gp[w]);
@@ -971,7 +980,7 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
 
 // Run one task to completion.  FEAT: the learned-policy / trace-recording
 // paths are compiled in (kept out of the plain kernel's register budget).
-template <int WM, bool FEAT>
+template <int WM, bool FEAT, bool GLOB, bool SEGC>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
                   long long t_start) {
@@ -1010,7 +1019,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         int st = node_test<WM>(I, L, lane, &bx);
         if (st == 2) { C.fails += 1; return; }
         dirty_all(L, n, lane);
-        if (propagate<WM>(I, L, layout, C, lane)) { C.fails += 1; return; }
+        if (propagate<WM, GLOB, SEGC>(I, L, layout, C, lane)) { C.fails += 1; return; }
         st = node_test<WM>(I, L, lane, &bx);
         if (st == 1) { record_solution<WM>(P, I, ctl, L, C, lane); return; }
         have_open = true;
@@ -1186,7 +1195,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         C.nodes += 1;
         C.stamp += 1;
         {
-            const bool failed = propagate<WM>(I, L, layout, C, lane);
+            const bool failed = propagate<WM, GLOB, SEGC>(I, L, layout, C, lane);
             if (failed) {
                 C.fails += 1;
                 if ((tracing || learned) && lane == 0) L.fails[F.x] += 1u;
@@ -1300,7 +1309,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // Persistent search kernel: every wavefront is a worker that pops tasks from
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
-template <int WM, bool TL, bool FEAT>
+template <int WM, bool TL, bool FEAT, bool GLOB, bool SEGC>
 __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     const int lane = lane_id();
@@ -1383,7 +1392,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
         if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
-        if (!uni(skip)) run_task<WM, FEAT>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+        if (!uni(skip)) run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
         if (lane == 0) add_i(&P.q->pending, -1);
@@ -1391,6 +1400,7 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     if (lane == 0 && idle) add_i(&P.q->idle, -1);
 }
 
+#if CUBICS_ONLY_WM == 1
 // Reset the queue and seed it with one ROOT task per instance.
 __global__ void init_kernel(SearchParams P) {
     const uint32_t cap = P.qmask + 1u;
@@ -1427,6 +1437,8 @@ __global__ void init_kernel(SearchParams P) {
     }
 }
 
+#endif
+
 // Root fixpoint of one instance (one wave): writes the domains and the verdict.
 template <int WM>
 __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsigned long long *revs) {
@@ -1460,7 +1472,7 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
     bool fail = node_test<WM>(I, L, lane, &bx) == 2;
     if (!fail) {
         dirty_all(L, n, lane);
-        fail = propagate<WM>(I, L, P.layout, C, lane);
+        fail = propagate<WM, true, true>(I, L, P.layout, C, lane);
     }
     wsync();
     for (int t = lane; t < nw; t += 64) out[t] = L.dom[t];
@@ -1472,19 +1484,21 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
 }
 
 // -------------------------------------------------- host-side launchers
-template <int WM, bool FEAT>
-static hipError_t launch_search_f(const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
-    if (tl)
-        hipLaunchKernelGGL((search_kernel<WM, true, FEAT>), dim3(blocks), dim3(64 * wpb), lds, st, P);
-    else
-        hipLaunchKernelGGL((search_kernel<WM, false, FEAT>), dim3(blocks), dim3(64 * wpb), lds, st, P);
-    return hipGetLastError();
+// Kernel variants: the learned / tracing kernel is general; the plain kernel
+// is specialised on the presence of global constraints and on the layout.
+template <int WM, bool TL>
+static const void *search_fn(int variant) {
+    switch (variant) {
+    case 0: return (const void *)search_kernel<WM, TL, false, false, false>;
+    case 1: return (const void *)search_kernel<WM, TL, false, false, true>;
+    case 2: return (const void *)search_kernel<WM, TL, false, true, false>;
+    case 3: return (const void *)search_kernel<WM, TL, false, true, true>;
+    default: return (const void *)search_kernel<WM, TL, true, true, true>;
+    }
 }
 template <int WM>
-static hipError_t launch_search_t(const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
-    const bool feat = P.trace_out != nullptr || P.branching == 1;
-    return feat ? launch_search_f<WM, true>(P, blocks, wpb, lds, tl, st)
-                : launch_search_f<WM, false>(P, blocks, wpb, lds, tl, st);
+static const void *search_fn_t(bool tl, int variant) {
+    return tl ? search_fn<WM, true>(variant) : search_fn<WM, false>(variant);
 }
 template <int WM>
 static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *failed,
@@ -1492,44 +1506,59 @@ static hipError_t launch_root_t(const SearchParams &P, uint32_t *out, int32_t *f
     hipLaunchKernelGGL(root_kernel<WM>, dim3(1), dim3(64), lds, st, P, out, failed, revs);
     return hipGetLastError();
 }
-template <int WM>
-static hipError_t occupancy_t(int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat) {
-    if (feat) {
-        if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true, true>, 64 * wpb, lds);
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false, true>, 64 * wpb, lds);
-    }
-    if (tl) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, true, false>, 64 * wpb, lds);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_kernel<WM, false, false>, 64 * wpb, lds);
+
+#define CUBICS_CAT2(a, b) a##b
+#define CUBICS_CAT(a, b) CUBICS_CAT2(a, b)
+
+const void *CUBICS_CAT(search_fn_w, CUBICS_ONLY_WM)(bool tl, int variant) {
+    return search_fn_t<CUBICS_ONLY_WM>(tl, variant);
+}
+hipError_t CUBICS_CAT(launch_root_w, CUBICS_ONLY_WM)(const SearchParams &P, uint32_t *out, int32_t *failed,
+                                                      unsigned long long *revs, size_t lds, hipStream_t st) {
+    return launch_root_t<CUBICS_ONLY_WM>(P, out, failed, revs, lds, st);
 }
 
-hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, hipStream_t st) {
+#if CUBICS_ONLY_WM == 1
+const void *search_fn_w2(bool tl, int variant);
+const void *search_fn_w4(bool tl, int variant);
+const void *search_fn_w8(bool tl, int variant);
+hipError_t launch_root_w2(const SearchParams &, uint32_t *, int32_t *, unsigned long long *, size_t, hipStream_t);
+hipError_t launch_root_w4(const SearchParams &, uint32_t *, int32_t *, unsigned long long *, size_t, hipStream_t);
+hipError_t launch_root_w8(const SearchParams &, uint32_t *, int32_t *, unsigned long long *, size_t, hipStream_t);
+
+static const void *search_fn_any(int wmax, bool tl, int variant) {
     switch (wmax) {
-    case 1: return launch_search_t<1>(P, blocks, wpb, lds, tl, st);
-    case 2: return launch_search_t<2>(P, blocks, wpb, lds, tl, st);
-    case 4: return launch_search_t<4>(P, blocks, wpb, lds, tl, st);
-    default: return launch_search_t<8>(P, blocks, wpb, lds, tl, st);
+    case 1: return search_fn_w1(tl, variant);
+    case 2: return search_fn_w2(tl, variant);
+    case 4: return search_fn_w4(tl, variant);
+    default: return search_fn_w8(tl, variant);
     }
+}
+// variant: 4 = learned/tracing; else bit 1 = globals present, bit 0 = SEG layout
+int search_variant(bool feat, bool glob, bool seg) { return feat ? 4 : (glob ? 2 : 0) + (seg ? 1 : 0); }
+
+hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
+                         hipStream_t st) {
+    const void *fn = search_fn_any(wmax, tl, variant);
+    void *args[] = {(void *)&P};
+    return hipLaunchKernel(fn, dim3(blocks), dim3(64 * wpb), args, lds, st);
 }
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st) {
     switch (wmax) {
-    case 1: return launch_root_t<1>(P, out, failed, revs, lds, st);
-    case 2: return launch_root_t<2>(P, out, failed, revs, lds, st);
-    case 4: return launch_root_t<4>(P, out, failed, revs, lds, st);
-    default: return launch_root_t<8>(P, out, failed, revs, lds, st);
+    case 1: return launch_root_w1(P, out, failed, revs, lds, st);
+    case 2: return launch_root_w2(P, out, failed, revs, lds, st);
+    case 4: return launch_root_w4(P, out, failed, revs, lds, st);
+    default: return launch_root_w8(P, out, failed, revs, lds, st);
     }
 }
 hipError_t launch_init(const SearchParams &P, hipStream_t st) {
     hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, P);
     return hipGetLastError();
 }
-hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, bool feat) {
-    switch (wmax) {
-    case 1: return occupancy_t<1>(blocks_per_cu, wpb, lds, tl, feat);
-    case 2: return occupancy_t<2>(blocks_per_cu, wpb, lds, tl, feat);
-    case 4: return occupancy_t<4>(blocks_per_cu, wpb, lds, tl, feat);
-    default: return occupancy_t<8>(blocks_per_cu, wpb, lds, tl, feat);
-    }
+hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, search_fn_any(wmax, tl, variant), 64 * wpb, lds);
 }
+#endif
 
 }  // namespace cubics
