@@ -20,7 +20,7 @@
 namespace cubics {
 hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
                          hipStream_t st);
-int search_variant(bool feat, bool glob, bool seg);
+int search_variant(int feat, bool glob, bool seg);
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
@@ -587,7 +587,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
-    const bool feat = L0.branching == CUBICS_BRANCH_LEARNED || (L0.trace_buf && L0.trace_capacity > 0);
+    const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
     const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG);
     HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, variant));
     if (bpc < 1) bpc = 1;

@@ -35,10 +35,13 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // 4 (lane / 16) + r.  If pre != nullptr, pre[4 t + r] receives the layer-1
 // pre-activation (with b1) of hidden unit 16 t + 4 (lane / 16) + r for row
 // lane % 16.
+// COMPACT: keep one hidden tile in flight at a time (fewer live registers,
+// for callers embedded in a larger kernel).
+template <bool COMPACT = false>
 __device__ __forceinline__ f32x4 mlp_tile(const PolicyDev &P, bf16x4 xT, int lane, float *pre) {
     const int col = lane & 15, kq = lane >> 4;
     f32x4 acc2 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+#pragma unroll(COMPACT ? 1 : 4)
     for (int t = 0; t < 4; ++t) {
         bf16x4 a1;
         const uint16_t *w = P.w1 + (size_t)(16 * t + col) * MLP_FPAD + 4 * kq;

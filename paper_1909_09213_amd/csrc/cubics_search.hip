@@ -917,6 +917,10 @@ template <int WM>
 DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, int depth, int lane, int fallback) {
     const int n = I.n;
     const int row = lane & 15, kq = lane >> 4;
+    // opaque copies of the weight pointers: keeps the (loop-invariant) weight
+    // loads inside this call instead of hoisted, and live, across the search
+    PolicyDev pol = P.policy;
+    asm volatile("" : "+s"(pol.w1), "+s"(pol.b1), "+s"(pol.w2), "+s"(pol.b2));
     u64 best = ~0ull;
     for (int base = 0; base < n; base += 16) {
         const int i = base + row;
@@ -929,13 +933,13 @@ DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, in
             const float f = (i < n && k < POLICY_F) ? var_feature(I, L, i, k, depth, pop) : 0.f;
             xT[j] = (short)f2bf(f);
         }
-        const f32x4 acc = mlp_tile(P.policy, xT, lane, nullptr);
+        const f32x4 acc = mlp_tile<true>(pol, xT, lane, nullptr);
         if (row == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ii = base + 4 * kq + r;
                 if (ii < n && var_pop<WM>(I, L, ii) >= 2) {
-                    const float y = acc[r] + *P.policy.b2;
+                    const float y = acc[r] + *pol.b2;
                     const uint32_t u = __float_as_uint(y);
                     const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
                     const u64 key = ((u64)ord << 32) | (u64)ii;
@@ -978,9 +982,10 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
     return (int)(kpick & 0xFFFFu);
 }
 
-// Run one task to completion.  FEAT: the learned-policy / trace-recording
-// paths are compiled in (kept out of the plain kernel's register budget).
-template <int WM, bool FEAT, bool GLOB, bool SEGC>
+// Run one task to completion.  FEAT: 0 plain first-fail, 1 learned policy,
+// 2 trace recording (each compiled separately to keep the plain kernel's
+// register budget).
+template <int WM, int FEAT, bool GLOB, bool SEGC>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
                   long long t_start) {
@@ -999,8 +1004,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     int depth = F0.depth;
     int since_poll = 0;
     int open_x = 0;
-    const bool tracing = FEAT && P.trace_out != nullptr;
-    const bool learned = FEAT && P.branching == 1;
+    const bool tracing = FEAT == 2 && P.trace_out != nullptr;
+    const bool learned = FEAT == 1 && P.branching == 1;
     if (tracing || learned) {
         for (int i = lane; i < n; i += 64) L.fails[i] = 0u;
         wsync();
@@ -1309,7 +1314,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // Persistent search kernel: every wavefront is a worker that pops tasks from
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
-template <int WM, bool TL, bool FEAT, bool GLOB, bool SEGC>
+template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC>
 __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     const int lane = lane_id();
@@ -1489,11 +1494,15 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
 template <int WM, bool TL>
 static const void *search_fn(int variant) {
     switch (variant) {
-    case 0: return (const void *)search_kernel<WM, TL, false, false, false>;
-    case 1: return (const void *)search_kernel<WM, TL, false, false, true>;
-    case 2: return (const void *)search_kernel<WM, TL, false, true, false>;
-    case 3: return (const void *)search_kernel<WM, TL, false, true, true>;
-    default: return (const void *)search_kernel<WM, TL, true, true, true>;
+    case 0: return (const void *)search_kernel<WM, TL, 0, false, false>;
+    case 1: return (const void *)search_kernel<WM, TL, 0, false, true>;
+    case 2: return (const void *)search_kernel<WM, TL, 0, true, false>;
+    case 3: return (const void *)search_kernel<WM, TL, 0, true, true>;
+    case 4: return (const void *)search_kernel<WM, TL, 1, false, false>;
+    case 5: return (const void *)search_kernel<WM, TL, 1, false, true>;
+    case 6: return (const void *)search_kernel<WM, TL, 1, true, false>;
+    case 7: return (const void *)search_kernel<WM, TL, 1, true, true>;
+    default: return (const void *)search_kernel<WM, TL, 2, true, true>;
     }
 }
 template <int WM>
@@ -1534,8 +1543,10 @@ static const void *search_fn_any(int wmax, bool tl, int variant) {
     default: return search_fn_w8(tl, variant);
     }
 }
-// variant: 4 = learned/tracing; else bit 1 = globals present, bit 0 = SEG layout
-int search_variant(bool feat, bool glob, bool seg) { return feat ? 4 : (glob ? 2 : 0) + (seg ? 1 : 0); }
+// variant: 8 = trace recording; else 4 * learned + 2 * globals present + SEG layout
+int search_variant(int feat, bool glob, bool seg) {
+    return feat == 2 ? 8 : 4 * (feat == 1) + (glob ? 2 : 0) + (seg ? 1 : 0);
+}
 
 hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
                          hipStream_t st) {
