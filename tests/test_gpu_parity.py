@@ -156,7 +156,7 @@ def test_limits_and_cap(ctx, cb):
 
 
 def test_split_invariance(ctx, cb):
-    inst = cspgen.rb(5, n=16, d=8, dens_pm=300, tight_pm=300)
+    inst = cspgen.rb(5, n=16, d=8, dens_pm=300, tight_pm=400)
     p = ctx.load(inst)
     tot = ctx.solve(p, cb.MODE_COUNT)
     parts = 0
