@@ -112,7 +112,7 @@ def test_root_fixpoint_rb_and_sweep(ctx, cb, layout):
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_rb_small_count(ctx, cb, layout):
     for idx in range(4):
-        inst = cspgen.rb(idx, n=20, d=8, dens_pm=300, tight_pm=350)
+        inst = cspgen.rb(idx, n=20, d=8, dens_pm=300, tight_pm=390)
         _say("rb small", idx, layout)
         ref = oracle.solve(inst, oracle.MODE_COUNT)
         r = ctx.solve(ctx.load(inst), cb.MODE_COUNT, layout=layout)
