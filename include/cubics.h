@@ -69,8 +69,15 @@ enum { CUBICS_MODE_FIRST = 0, CUBICS_MODE_ALL = 1, CUBICS_MODE_COUNT = 2 };
 enum { CUBICS_SAT = 0, CUBICS_UNSAT = 1, CUBICS_LIMIT = 2, CUBICS_CANCELLED = 3 };
 /* branching heuristics */
 enum { CUBICS_BRANCH_FIRST_FAIL = 0, CUBICS_BRANCH_LEARNED = 1 };
-/* revision layouts for binary constraints (see cubics_solve) */
-enum { CUBICS_LAYOUT_AUTO = 0, CUBICS_LAYOUT_LANE = 1, CUBICS_LAYOUT_SEG = 2 };
+/* revision layouts for binary constraints:
+   LANE  one lane per directed propagator, domains in LDS;
+   SEG   one lane per value of the revised variable (ballot-assembled), domains in LDS;
+   VAR   one lane per variable, domains in registers (instances with at most 64
+         variables of at most 32 values, binary constraints only, one constraint
+         per variable pair; other instances fall back to LANE);
+   AUTO  the autotuned choice for the instance's shape, else VAR when usable,
+         else SEG for domains wider than 24 values, else LANE. */
+enum { CUBICS_LAYOUT_AUTO = 0, CUBICS_LAYOUT_LANE = 1, CUBICS_LAYOUT_SEG = 2, CUBICS_LAYOUT_VAR = 3 };
 
 /* Supported range: 1 <= d_i <= 256 values per variable (at most 8 32-bit
    words per domain); n <= 1024 variables with n * ceil(dmax/32) <= 4096;
@@ -209,8 +216,7 @@ int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
                        const cubics_limits *limits, cubics_result *results);
 
 /* Autotuner: run these problems for time_ms of search under each revision
-   layout (LANE: one lane per propagator; SEG: one lane per value of the
-   revised variable, ballot-assembled), measure search nodes per ms, and
+   layout they admit (LANE, SEG, VAR), measure search nodes per ms, and
    remember the faster layout for the first problem's shape bucket (domain
    words, domain size, variable count, constraint kinds).  Later solves with
    layout AUTO on the same context use it.  *chosen (nullable) receives it. */

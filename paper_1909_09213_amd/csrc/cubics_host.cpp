@@ -20,7 +20,7 @@
 namespace cubics {
 hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
                          hipStream_t st);
-int search_variant(int feat, bool glob, bool seg);
+int search_variant(int feat, bool glob, bool seg, bool var);
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
@@ -388,6 +388,27 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
         feat[4 * i + 2] = 1.f / (float)dsize[i];
     }
 
+    // ---- VAR layout (one lane per variable): dense pair matrix of units
+    bool var_ok = n >= 1 && n <= 64 && W == 1 && gdesc.empty();
+    std::vector<int32_t> pairs;
+    if (var_ok) {
+        pairs.assign((size_t)n * n * 2, 0);
+        for (const Unit &u : sorted) {
+            const int t = u.tt & 0xFFFFFF, ty = u.tt >> 24, j = u.src;
+            int32_t *e = &pairs[((size_t)j * n + t) * 2];
+            if (e[0] != 0) { var_ok = false; break; }  // two constraints on one pair
+            int32_t prm = 0;
+            if (ty == U_TABLE) prm = u.p1;
+            else if (ty == U_QUEENS) {
+                if (u.p0 < 0 || u.p0 >= (1 << 15) || u.p1 < -(1 << 15) || u.p1 >= (1 << 15)) { var_ok = false; break; }
+                prm = (u.p0 << 16) | (u.p1 & 0xFFFF);
+            } else prm = u.p0;
+            e[0] = ty;
+            e[1] = prm;
+        }
+    }
+    if (!var_ok) pairs.assign(2, 0);
+
     // ---- pack and upload
     Packer pk;
     std::vector<int32_t> lov(lo, lo + n);
@@ -408,6 +429,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     if (unary.empty()) { unary.push_back(0); unary.push_back(0); }
     const size_t o_un = pk.add(unary.data(), unary.size() * 4);
     const size_t o_ft = pk.add(feat.data(), feat.size() * 4);
+    const size_t o_pairs = pk.add(pairs.data(), pairs.size() * 4);
     pk.add(nullptr, 0, 16);
     pk.bytes.resize((pk.bytes.size() + 15) / 16 * 16, 0);
 
@@ -459,6 +481,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     I.gcoef = (const int64_t *)(b8 + o_gc);
     I.unary = (const int32_t *)(b8 + o_un);
     I.feat_static = (const float *)(b8 + o_ft);
+    I.pairs = (const int2 *)(b8 + o_pairs);
+    I.var_ok = var_ok ? 1 : 0;
     I.blob = (const uint32_t *)blob;
     I.blob_words = (uint32_t)((pk.bytes.size() + 15) / 16 * 4);
     char key[160];
@@ -520,18 +544,22 @@ Geometry geometry(cubics_prob *const *probs, int B) {
 }
 
 int choose_layout(cubics_prob *const *probs, int B, int requested) {
-    if (requested == CUBICS_LAYOUT_LANE || requested == CUBICS_LAYOUT_SEG) return requested;
+    if (requested == CUBICS_LAYOUT_LANE || requested == CUBICS_LAYOUT_SEG || requested == CUBICS_LAYOUT_VAR)
+        return requested;
     // AUTO: the autotuned choice of the first instance's shape bucket, else a
-    // rule: lane-per-value segments pay off once domains are wide
+    // rule: registers when the instance is small enough, lane-per-value
+    // segments once domains are wide
     cubics_ctx *ctx = probs[0]->ctx;
     auto it = ctx->tuned.find(probs[0]->bucket);
     if (it != ctx->tuned.end()) return it->second;
     int dmax = 1;
-    bool seg_ok = true;
+    bool seg_ok = true, var_ok = true;
     for (int b = 0; b < B; ++b) {
         dmax = std::max(dmax, probs[b]->dmax);
         seg_ok &= probs[b]->dmax <= 64;
+        var_ok &= probs[b]->dev.var_ok != 0;
     }
+    if (var_ok) return CUBICS_LAYOUT_VAR;
     return (seg_ok && dmax > 24) ? CUBICS_LAYOUT_SEG : CUBICS_LAYOUT_LANE;
 }
 
@@ -573,13 +601,18 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const int layout = choose_layout(probs, B, L0.layout);
 
     // ---- workers: fill the device with co-resident wavefronts.  A single
-    // instance whose packed tables fit is staged in LDS once per workgroup.
+    // instance whose packed tables fit is staged in LDS once per workgroup;
+    // the register-resident VAR path uses 8 workers per workgroup to share it.
     const size_t LDS_WG_MAX = 64 * 1024;
-    int wpb = 4;
+    const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
+    bool var_all = G.wmax == 1;
+    for (int b = 0; b < B && var_all; ++b) var_all = probs[b]->dev.var_ok != 0;
+    const bool use_var = feat == 0 && layout == CUBICS_LAYOUT_VAR && var_all;
+    const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG, use_var);
+    int wpb = use_var ? 8 : 4;
     const size_t per_wave = (size_t)G.lds_words * 4;
     const size_t tab_bytes = (B == 1) ? (size_t)probs[0]->dev.blob_words * 4 : 0;
-    bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + per_wave * wpb <= LDS_WG_MAX;
-    if (L0.tables_in_lds == 2) tl = false;
+    bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + per_wave <= LDS_WG_MAX;
     size_t lds = (tl ? tab_bytes : 0) + per_wave * wpb;
     while (wpb > 1 && lds > LDS_WG_MAX) {
         wpb /= 2;
@@ -587,8 +620,6 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
-    const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
-    const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG);
     HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, variant));
     if (bpc < 1) bpc = 1;
     int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
@@ -753,10 +784,11 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
 extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
                                int64_t time_ms, int32_t *chosen) {
     if (!probs || B < 1 || !probs[0] || time_ms < 1) return fail(CUBICS_EINVAL, "bad autotune arguments");
-    bool seg_ok = true;
+    bool seg_ok = true, var_ok = true;
     for (int b = 0; b < B; ++b) {
         if (!probs[b]) return fail(CUBICS_EINVAL, "prob[%d] is NULL", b);
         seg_ok &= probs[b]->dmax <= 64;
+        var_ok &= probs[b]->dev.var_ok != 0;
     }
     std::vector<cubics_limits> lim(B);
     for (int b = 0; b < B; ++b) {
@@ -772,8 +804,11 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
     std::vector<cubics_result> res(B);
     int best = CUBICS_LAYOUT_LANE;
     double best_rate = -1.0;
-    const int cands[2] = {CUBICS_LAYOUT_LANE, CUBICS_LAYOUT_SEG};
-    for (int ci = 0; ci < (seg_ok ? 2 : 1); ++ci) {
+    int cands[3], nc = 0;
+    cands[nc++] = CUBICS_LAYOUT_LANE;
+    if (seg_ok) cands[nc++] = CUBICS_LAYOUT_SEG;
+    if (var_ok) cands[nc++] = CUBICS_LAYOUT_VAR;
+    for (int ci = 0; ci < nc; ++ci) {
         lim[0].layout = cands[ci];
         // a warm-up run, then the timed one
         for (int rep = 0; rep < 2; ++rep) {

@@ -1289,6 +1289,286 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     }
 }
 
+
+// ------------------------------------------------- VAR layout (n <= 64, W = 1)
+//
+// One lane per variable: lane i keeps D_i in a register for the whole node.
+// A dirty variable j is broadcast with readlane, and every lane t that shares
+// a constraint with j revises its own domain against D_j in the same
+// instruction (its unit is the dense pair entry [j][t]).  Changes update the
+// register at once and feed the next dirty set through a ballot, so a node
+// needs no LDS traffic for domains or dirty sets.
+
+DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int lane) {
+    const int n = I.n;
+    while (cur) {
+        u64 nxt = 0;
+        while (cur) {
+            const int j = __ffsll((long long)cur) - 1;
+            cur &= cur - 1;
+            const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)d, j);
+            int2 e = {0, 0};
+            if (lane < n) e = I.pairs[j * n + lane];
+            uint32_t nd = d;
+            if (e.x != 0) {
+                const int ty = e.x;
+                if (ty == U_TABLE) {
+                    uint32_t acc = 0u, bits = dj;
+                    while (bits) {  // uniform: dj is the same in every lane
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        acc |= I.rows[e.y + b];
+                    }
+                    nd = d & acc;
+                } else if (ty == U_NEQ) {
+                    if (__popc(dj) == 1) nd = d & ~bit_in_word(__ffs(dj) - 1 + e.y, 0);
+                } else if (ty == U_LT_UB) {
+                    nd = d & mask_le(31 - __clz(dj) + e.y - 1, 0);
+                } else if (ty == U_LT_LB) {
+                    nd = d & mask_ge(__ffs(dj) - 1 - e.y + 1, 0);
+                } else {  // QUEENS
+                    if (__popc(dj) <= 3) {
+                        const int kq = e.y >> 16;
+                        const int dl = (int)(short)(e.y & 0xFFFF);
+                        uint32_t uns = 0xFFFFFFFFu, bits = dj;
+                        while (bits) {
+                            const int b = __ffs(bits) - 1 + dl;
+                            bits &= bits - 1;
+                            uns &= bit_in_word(b, 0) | bit_in_word(b + kq, 0) | bit_in_word(b - kq, 0);
+                        }
+                        nd = d & ~uns;
+                    }
+                }
+                C.rev += 1;
+                C.bytes += rev_bytes(ty, 1, __popc(d), nd != d);
+            }
+            const bool ch = nd != d;
+            d = nd;
+            const u64 chm = __ballot(ch);
+            if (chm) {
+                if (__ballot(ch && nd == 0u)) return true;
+                nxt |= chm;
+            }
+        }
+        cur = nxt;
+    }
+    return false;
+}
+
+// first-fail over the register domains: 0 open (*bx), 1 solution, 2 failed
+DEV int node_test_var(int n, uint32_t d, int lane, int *bx) {
+    const int pop = lane < n ? __popc(d) : 0;
+    if (__ballot(lane < n && pop == 0)) return 2;
+    const u64 open = __ballot(pop >= 2);
+    if (!open) return 1;
+    for (int p = 2; p <= 32; ++p) {
+        const u64 m = __ballot(pop == p);
+        if (m) {
+            *bx = __ffsll((long long)m) - 1;
+            return 0;
+        }
+    }
+    return 1;
+}
+
+template <int WM>
+DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
+                      Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
+                      long long t_start) {
+    const int n = I.n;
+    const uint32_t FW = P.frame_words;
+    int sp = 0;
+    Frame<WM> F;
+    bool have_open = false, need_restore = false;
+    int depth = F0.depth;
+    int since_poll = 0;
+    int open_x = 0;
+    uint32_t d = lane < n ? L.dom[lane] : 0u;
+    uint32_t snapc = 0u;
+    bool snap_valid = false;
+
+    if (kind == K_ROOT) {
+        for (int t = 0; t < I.n_unary; ++t) {
+            const int v = I.unary[2 * t], off = I.unary[2 * t + 1];
+            if (lane == v) d &= I.rows[off];
+        }
+        C.nodes += 1;
+        C.stamp += 1;
+        int bx = 0;
+        if (node_test_var(n, d, lane, &bx) == 2) { C.fails += 1; return; }
+        const u64 all = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+        if (propagate_var(I, d, all, C, lane)) { C.fails += 1; return; }
+        const int st = node_test_var(n, d, lane, &bx);
+        if (st == 1) {
+            if (lane < n) L.dom[lane] = d;
+            wsync();
+            record_solution<WM>(P, I, ctl, L, C, lane);
+            return;
+        }
+        have_open = true;
+        open_x = bx;
+        depth = 0;
+    } else {
+        F = F0;
+        if (lane < n) trail[FRAME_HDR + lane] = d;
+        snapc = d;
+        snap_valid = true;
+        frame_store_meta<WM>(trail, F, lane);
+        sp = 1;
+    }
+
+    for (;;) {
+        if (have_open) {
+            have_open = false;
+            const int x = open_x;
+            bool split = false;
+            if (P.split_target > 0) {
+                long long prod = 0;
+                if (lane == 0) prod = (long long)ld_rlx_u64(&P.q->produced);
+                prod = unill(prod);
+                if (prod < P.split_target) split = true;
+            }
+            uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)d, x);
+            if (split) {
+                if (lane < n) L.dom[lane] = d;
+                wsync();
+                uint32_t rem = dx;
+                int pushed = 0;
+                while (rem) {
+                    const uint32_t lowb = rem & (0u - rem);
+                    uint32_t one[WM];
+#pragma unroll
+                    for (int q = 0; q < WM; ++q) one[q] = q == 0 ? lowb : 0u;
+                    if (!push_frame<WM>(P, b, x, depth, one, L.dom, n, lane)) break;
+                    rem &= ~lowb;
+                    ++pushed;
+                }
+                if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
+                if (!rem) goto next_child;
+                dx = rem;
+            }
+            {
+                if (sp > 0 && lane == 0) trail[(size_t)(sp - 1) * FW + 4] = F.v[0];
+                uint32_t *f = trail + (size_t)sp * FW;
+                if (lane < n) f[FRAME_HDR + lane] = d;
+                C.bytes += lane == 0 ? 4ull * n : 0ull;
+                snapc = d;
+                snap_valid = true;
+                F.x = x;
+                F.depth = depth;
+                F.v[0] = dx;
+#pragma unroll
+                for (int k = 1; k < WM; ++k) F.v[k] = 0u;
+                frame_store_meta<WM>(f, F, lane);
+                ++sp;
+                need_restore = false;
+            }
+        }
+    next_child:
+        for (;;) {
+            if (sp == 0) return;
+            if (F.v[0] == 0u) {
+                --sp;
+                if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
+                need_restore = true;
+                snap_valid = false;
+                continue;
+            }
+            break;
+        }
+        {
+            const int vi = __ffs(F.v[0]) - 1;
+            F.v[0] &= F.v[0] - 1;
+            if (need_restore) {
+                if (!snap_valid) {
+                    const uint32_t *f = trail + (size_t)(sp - 1) * FW;
+                    snapc = lane < n ? f[FRAME_HDR + lane] : 0u;
+                    snap_valid = true;
+                }
+                d = snapc;
+                C.bytes += lane == 0 ? 4ull * n : 0ull;
+            }
+            need_restore = true;
+            if (lane == F.x) d = 1u << vi;
+            depth = F.depth + 1;
+        }
+        C.nodes += 1;
+        C.stamp += 1;
+        if (propagate_var(I, d, 1ull << F.x, C, lane)) {
+            C.fails += 1;
+        } else {
+            int bx = 0;
+            const int st = node_test_var(n, d, lane, &bx);
+            if (st == 1) {
+                const bool store = P.mode == 0 || (I.sol_buf && I.sol_cap > 0);
+                if (store) {
+                    if (lane < n) L.dom[lane] = d;
+                    wsync();
+                }
+                record_solution<WM>(P, I, ctl, L, C, lane);
+                if (P.mode == 0) return;
+            } else {
+                have_open = true;
+                open_x = bx;
+            }
+        }
+        if (++since_poll >= POLL) {
+            since_poll = 0;
+            int stop = 0, idle = 0;
+            u64 qlen = 0;
+            if (lane == 0) {
+                stop = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
+                if (P.donate) {
+                    idle = ld_rlx_i(&P.q->idle);
+                    qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
+                }
+            }
+            if (uni(stop)) return;
+            if (I.max_nodes) {
+                u64 tot = 0;
+                if (lane == 0) tot = add_u64(&ctl->nodes, C.nodes) + C.nodes;
+                tot = uni64(tot);
+                C.nodes = 0;
+                if (tot >= I.max_nodes) {
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); }
+                    return;
+                }
+            }
+            if (P.time_ticks || P.cancel) {
+                int st2 = 0;
+                if (lane == 0) {
+                    if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
+                    if (P.cancel && *P.cancel) st2 = 3;
+                    if (st2) { P.q->stop_reason = st2; st_rel_i(&P.q->stop, 1); }
+                }
+                if (uni(st2)) return;
+            }
+            idle = uni(idle);
+            if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
+                int tsel = -1;
+                for (int base = 0; base < sp - 1 && tsel < 0; base += 64) {
+                    const int t = base + lane;
+                    const bool nz = t < sp - 1 && trail[(size_t)t * FW + 4] != 0u;
+                    const u64 m = __ballot(nz);
+                    if (m) tsel = base + __ffsll((long long)m) - 1;
+                }
+                if (tsel < 0 && F.v[0] != 0u) tsel = sp - 1;
+                if (tsel >= 0) {
+                    uint32_t *f = trail + (size_t)tsel * FW;
+                    Frame<WM> D;
+                    frame_load_meta<WM>(f, D);
+                    if (tsel == sp - 1) D = F;
+                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, n, lane)) {
+                        if (lane == 0) f[4] = 0u;
+                        if (tsel == sp - 1) F.v[0] = 0u;
+                        C.steals += 1;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // A copy of an instance descriptor whose array pointers point into `tab`, a
 // copy of the instance's packed blob (used to stage one instance in LDS).
 DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
@@ -1307,6 +1587,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
     I.gcoef = (const int64_t *)(t0 + ((const char *)g.gcoef - b0));
     I.unary = (const int32_t *)(t0 + ((const char *)g.unary - b0));
     I.feat_static = (const float *)(t0 + ((const char *)g.feat_static - b0));
+    I.pairs = (const int2 *)(t0 + ((const char *)g.pairs - b0));
     I.blob = tab;
     return I;
 }
@@ -1314,8 +1595,8 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // Persistent search kernel: every wavefront is a worker that pops tasks from
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
-template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC>
-__global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
+template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC, bool VAR = false>
+__global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -1397,7 +1678,12 @@ __global__ __launch_bounds__(256) void search_kernel(SearchParams P) {
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
         if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
-        if (!uni(skip)) run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+        if (!uni(skip)) {
+            if (VAR)
+                run_task_var<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+            else
+                run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+        }
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
         if (lane == 0) add_i(&P.q->pending, -1);
@@ -1502,6 +1788,7 @@ static const void *search_fn(int variant) {
     case 5: return (const void *)search_kernel<WM, TL, 1, false, true>;
     case 6: return (const void *)search_kernel<WM, TL, 1, true, false>;
     case 7: return (const void *)search_kernel<WM, TL, 1, true, true>;
+    case 9: return (const void *)search_kernel<WM, TL, 0, false, false, WM == 1>;
     default: return (const void *)search_kernel<WM, TL, 2, true, true>;
     }
 }
@@ -1543,8 +1830,10 @@ static const void *search_fn_any(int wmax, bool tl, int variant) {
     default: return search_fn_w8(tl, variant);
     }
 }
-// variant: 8 = trace recording; else 4 * learned + 2 * globals present + SEG layout
-int search_variant(int feat, bool glob, bool seg) {
+// variant: 9 = VAR layout (plain); 8 = trace recording; else 4 * learned +
+// 2 * globals present + SEG layout
+int search_variant(int feat, bool glob, bool seg, bool var) {
+    if (feat == 0 && var) return 9;
     return feat == 2 ? 8 : 4 * (feat == 1) + (glob ? 2 : 0) + (seg ? 1 : 0);
 }
 

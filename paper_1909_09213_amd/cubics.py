@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcubics.so")
 
 MODE_FIRST, MODE_ALL, MODE_COUNT = 0, 1, 2
-LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_SEG = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_SEG, LAYOUT_VAR = 0, 1, 2, 3
 BRANCH_FIRST_FAIL, BRANCH_LEARNED = 0, 1
 VERDICTS = {0: "SAT", 1: "UNSAT", 2: "LIMIT", 3: "CANCELLED"}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}
@@ -219,7 +219,7 @@ class Context:
 
     # ------------------------------------------------------------ autotune
     def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, **kw) -> int:
-        """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG)."""
+        """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG, 3 VAR)."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()

@@ -12,7 +12,7 @@ import oracle
 
 pytestmark = pytest.mark.gpu
 
-LAYOUTS = [1, 2]  # LANE, SEG
+LAYOUTS = [1, 2, 3]  # LANE, SEG, VAR
 
 
 @pytest.fixture(scope="module")
