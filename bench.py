@@ -134,6 +134,10 @@ def main():
     q13 = ctx.load(cspgen.queens(13))
     slices = {v: ctx.load(rb_slice(inst, v)) for v in range(16)}
 
+    # the library's autotuner picks the revision layout for each shape (untimed)
+    tuned = {"rb": ctx.autotune([slices[15]], cb.MODE_COUNT, time_ms=400),
+             "queens13": ctx.autotune([q13], cb.MODE_COUNT, time_ms=100)}
+
     def step(v):
         r1 = ctx.solve(slices[v], cb.MODE_COUNT, layout=args.layout, split_target=args.split)
         r2 = ctx.solve(q13, cb.MODE_COUNT, layout=args.layout, split_target=args.split)
@@ -179,7 +183,8 @@ def main():
                                "(195 tables, 90/256 pairs forbidden, seed 2 index 0) count-all in "
                                "16 x0-slices, + 13-queens count-all",
                    "slices_timed": list(range(args.steps)),
-                   "layout": args.layout, "split_target": args.split},
+                   "layout": args.layout, "split_target": args.split,
+                   "autotuned_layout": tuned},
         "revisions_per_s": revs / dt,
         "solutions": {"rb_slices": [r.count for r in rb_res], "queens13": q_res[0].count},
         "nodes": {"rb_slices": [r.nodes for r in rb_res], "queens13": q_res[0].nodes},

@@ -483,6 +483,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     I.feat_static = (const float *)(b8 + o_ft);
     I.pairs = (const int2 *)(b8 + o_pairs);
     I.var_ok = var_ok ? 1 : 0;
+    I.unit_types = 0;
+    for (const Unit &u : sorted) I.unit_types |= 1 << (u.tt >> 24);
     I.blob = (const uint32_t *)blob;
     I.blob_words = (uint32_t)((pk.bytes.size() + 15) / 16 * 4);
     char key[160];

@@ -60,6 +60,8 @@ struct InstDev {
     uint32_t blob_words;         // its size in 32-bit words
     int32_t var_ok;              // VAR layout usable: n <= 64, one word per domain,
                                  // binary constraints only, one constraint per pair
+    int32_t unit_types;          // bit t set iff some binary unit has type t
+    int32_t pad1;
     // per-instance solve settings (written by the host for each solve)
     int32_t *sol_buf;
     uint64_t sol_cap;

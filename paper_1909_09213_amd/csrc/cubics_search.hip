@@ -1299,34 +1299,78 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
 // register at once and feed the next dirty set through a ballot, so a node
 // needs no LDS traffic for domains or dirty sets.
 
-DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int lane) {
+// Revision of target lane t against the broadcast source domain dj (pair
+// entry e = {type, param}); generic over the unit types.
+DEV uint32_t revise_var_generic(const InstDev &I, int2 e, uint32_t d, uint32_t dj) {
+    const int ty = e.x;
+    if (ty == U_TABLE) {
+        uint32_t acc = 0u, bits = dj;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            acc |= I.rows[e.y + b];
+        }
+        return d & acc;
+    } else if (ty == U_NEQ) {
+        return __popc(dj) == 1 ? d & ~bit_in_word(__ffs(dj) - 1 + e.y, 0) : d;
+    } else if (ty == U_LT_UB) {
+        return d & mask_le(31 - __clz(dj) + e.y - 1, 0);
+    } else if (ty == U_LT_LB) {
+        return d & mask_ge(__ffs(dj) - 1 - e.y + 1, 0);
+    } else if (ty == U_QUEENS) {
+        if (__popc(dj) > 3) return d;
+        const int kq = e.y >> 16;
+        const int dl = (int)(short)(e.y & 0xFFFF);
+        uint32_t uns = 0xFFFFFFFFu, bits = dj;
+        while (bits) {
+            const int b = __ffs(bits) - 1 + dl;
+            bits &= bits - 1;
+            uns &= bit_in_word(b, 0) | bit_in_word(b + kq, 0) | bit_in_word(b - kq, 0);
+        }
+        return d & ~uns;
+    }
+    return d;
+}
+
+// Support union of the rows of the source values in dj (uniform across the
+// wave), four independent row loads in flight at a time.
+DEV uint32_t table_union(const uint32_t *rows, uint32_t dj) {
+    uint32_t acc = 0u, bits = dj;
+    while (bits) {
+        const int b0 = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int b1 = bits ? __ffs(bits) - 1 : b0;
+        bits &= bits - 1;
+        const int b2 = bits ? __ffs(bits) - 1 : b0;
+        bits &= bits - 1;
+        const int b3 = bits ? __ffs(bits) - 1 : b0;
+        bits &= bits - 1;
+        acc |= rows[b0] | rows[b1] | rows[b2] | rows[b3];
+    }
+    return acc;
+}
+
+// TYPES: 0 generic, 1 table units only, 2 queens units only (uniform choice).
+template <int TYPES>
+DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int lane) {
     const int n = I.n;
     while (cur) {
         u64 nxt = 0;
+        int j = __ffsll((long long)cur) - 1;
+        int2 e = {0, 0};
+        if (lane < n) e = I.pairs[j * n + lane];
         while (cur) {
-            const int j = __ffsll((long long)cur) - 1;
             cur &= cur - 1;
+            // prefetch the pair entry of the next dirty variable
+            const int jn = cur ? __ffsll((long long)cur) - 1 : j;
+            int2 en = {0, 0};
+            if (lane < n) en = I.pairs[jn * n + lane];
             const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)d, j);
-            int2 e = {0, 0};
-            if (lane < n) e = I.pairs[j * n + lane];
             uint32_t nd = d;
             if (e.x != 0) {
-                const int ty = e.x;
-                if (ty == U_TABLE) {
-                    uint32_t acc = 0u, bits = dj;
-                    while (bits) {  // uniform: dj is the same in every lane
-                        const int b = __ffs(bits) - 1;
-                        bits &= bits - 1;
-                        acc |= I.rows[e.y + b];
-                    }
-                    nd = d & acc;
-                } else if (ty == U_NEQ) {
-                    if (__popc(dj) == 1) nd = d & ~bit_in_word(__ffs(dj) - 1 + e.y, 0);
-                } else if (ty == U_LT_UB) {
-                    nd = d & mask_le(31 - __clz(dj) + e.y - 1, 0);
-                } else if (ty == U_LT_LB) {
-                    nd = d & mask_ge(__ffs(dj) - 1 - e.y + 1, 0);
-                } else {  // QUEENS
+                if (TYPES == 1) {
+                    nd = d & table_union(I.rows + e.y, dj);
+                } else if (TYPES == 2) {
                     if (__popc(dj) <= 3) {
                         const int kq = e.y >> 16;
                         const int dl = (int)(short)(e.y & 0xFFFF);
@@ -1338,9 +1382,11 @@ DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int 
                         }
                         nd = d & ~uns;
                     }
+                } else {
+                    nd = revise_var_generic(I, e, d, dj);
                 }
                 C.rev += 1;
-                C.bytes += rev_bytes(ty, 1, __popc(d), nd != d);
+                C.bytes += rev_bytes(e.x, 1, __popc(d), nd != d);
             }
             const bool ch = nd != d;
             d = nd;
@@ -1349,10 +1395,18 @@ DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int 
                 if (__ballot(ch && nd == 0u)) return true;
                 nxt |= chm;
             }
+            j = jn;
+            e = en;
         }
         cur = nxt;
     }
     return false;
+}
+
+DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int lane) {
+    if (I.unit_types == (1 << U_TABLE)) return propagate_var_t<1>(I, d, cur, C, lane);
+    if (I.unit_types == (1 << U_QUEENS)) return propagate_var_t<2>(I, d, cur, C, lane);
+    return propagate_var_t<0>(I, d, cur, C, lane);
 }
 
 // first-fail over the register domains: 0 open (*bx), 1 solution, 2 failed
