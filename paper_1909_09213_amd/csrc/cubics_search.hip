@@ -869,7 +869,7 @@ DEV void flush(InstCtl *ctl, Counters &C, int lane) {
     C.rev = C.bytes = 0;
 }
 
-constexpr int POLL = 64;  // nodes between checks of stop flags and donation requests
+constexpr int POLL = 128;  // nodes between checks of stop flags and donation requests
 
 
 // ------------------------------------------------------ branching policy
@@ -1686,6 +1686,9 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     const long long t_start = (long long)wall_clock64();
     Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
     bool idle = false;
+    // Idle workers back off exponentially (up to ~27 us between polls): with
+    // thousands of waves polling the same queue words, the polls themselves
+    // would otherwise saturate the memory-side atomics the busy workers need.
     int backoff = 1;
     for (;;) {
         uint32_t cell = 0, pos = 0;
@@ -1700,8 +1703,8 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
             }
             idle = true;
             if (uni(pend) == 0) break;
-            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(8);
-            backoff = backoff < 16 ? backoff * 2 : 16;
+            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(32);
+            backoff = backoff < 32 ? backoff * 2 : 32;
             continue;
         }
         backoff = 1;
