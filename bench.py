@@ -135,8 +135,12 @@ def main():
     slices = {v: ctx.load(rb_slice(inst, v)) for v in range(16)}
 
     # the library's autotuner picks the revision layout for each shape (untimed)
-    tuned = {"rb": ctx.autotune([slices[15]], cb.MODE_COUNT, time_ms=400),
-             "queens13": ctx.autotune([q13], cb.MODE_COUNT, time_ms=100)}
+    tuned = {}
+    for name, p, t in (("rb", slices[15], 400), ("queens13", q13, 100)):
+        chosen, div, rates = ctx.autotune([p], cb.MODE_COUNT, time_ms=t, rates=True)
+        names = {1: "lane", 2: "seg", 3: "var"}
+        tuned[name] = {"chosen": names[chosen], "worker_divisor": div,
+                       "nodes_per_ms": {f"{names[k]}/{d}": round(v) for (k, d), v in rates.items()}}
 
     def step(v):
         r1 = ctx.solve(slices[v], cb.MODE_COUNT, layout=args.layout, split_target=args.split)

@@ -110,7 +110,8 @@ typedef struct {
                                 among the 4 candidates with the smallest domains */
     float *trace_buf;        /* device, caller-owned [trace_capacity][8] floats, or NULL.
                                 Each completed subtree under a branching records the
-                                branching variable's 5 features, the depth, 0 and the label
+                                branching variable's 5 features, the depth, the instance's
+                                index in the batch and the label
                                 log2(1 + nodes below the branching).  Subtrees that were
                                 split or donated are not recorded. */
     uint64_t trace_capacity;
@@ -216,12 +217,20 @@ int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
                        const cubics_limits *limits, cubics_result *results);
 
 /* Autotuner: run these problems for time_ms of search under each revision
-   layout they admit (LANE, SEG, VAR), measure search nodes per ms, and
-   remember the faster layout for the first problem's shape bucket (domain
-   words, domain size, variable count, constraint kinds).  Later solves with
-   layout AUTO on the same context use it.  *chosen (nullable) receives it. */
+   layout they admit (LANE, SEG, VAR) and each of CUBICS_AUTOTUNE_DIVS worker
+   counts (the occupancy-limited maximum divided by 1, 2 and 4: a small
+   search tree finishes sooner on fewer workers, whose idle polls and task
+   hand-offs cost less), measure search nodes per ms, and remember the fastest
+   pair for the first problem's shape bucket (domain words, domain size,
+   variable count, constraint kinds).  Later solves with layout AUTO and
+   workers 0 on the same context use it.  *chosen and *chosen_div (nullable)
+   receive the layout and the divisor; rates (nullable, host,
+   3 * CUBICS_AUTOTUNE_DIVS doubles) receives the measured nodes per ms at
+   [(layout - 1) * CUBICS_AUTOTUNE_DIVS + divisor index], 0 where a layout is
+   not admitted.  The runs use limits[] (NULL: none) with time_ms added. */
+enum { CUBICS_AUTOTUNE_DIVS = 3 };
 int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
-                    int64_t time_ms, int32_t *chosen);
+                    int64_t time_ms, int32_t *chosen, int32_t *chosen_div, double *rates);
 
 /* -------------------------------------------------------- learned policy
  * The branching network (variable ordering, used when branching == LEARNED):

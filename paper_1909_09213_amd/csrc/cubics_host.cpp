@@ -85,7 +85,11 @@ struct cubics_ctx {
     DevBuf inst, ctl, q, qseq, qdata, trail, rootout, tracecnt;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
-    std::map<std::string, int> tuned;  // shape bucket -> layout
+    struct Tuned {
+        int layout;  // revision layout
+        int div;     // workers = the occupancy-limited maximum / div
+    };
+    std::map<std::string, Tuned> tuned;  // shape bucket -> autotuned choice
     std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
     hipStream_t graph_stream = nullptr;  // capture stream when the caller's is the null stream
 };
@@ -388,26 +392,30 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
         feat[4 * i + 2] = 1.f / (float)dsize[i];
     }
 
-    // ---- VAR layout (one lane per variable): dense pair matrix of units
+    // ---- VAR layout (one lane per variable): dense pair matrix of units,
+    // row stride 64, one packed word per entry
     bool var_ok = n >= 1 && n <= 64 && W == 1 && gdesc.empty();
-    std::vector<int32_t> pairs;
+    std::vector<uint32_t> pairs;
     if (var_ok) {
-        pairs.assign((size_t)n * n * 2, 0);
+        pairs.assign((size_t)n * 64, 0u);
+        const int32_t P28 = 1 << 27;  // parameters are 28-bit signed
         for (const Unit &u : sorted) {
             const int t = u.tt & 0xFFFFFF, ty = u.tt >> 24, j = u.src;
-            int32_t *e = &pairs[((size_t)j * n + t) * 2];
-            if (e[0] != 0) { var_ok = false; break; }  // two constraints on one pair
-            int32_t prm = 0;
-            if (ty == U_TABLE) prm = u.p1;
-            else if (ty == U_QUEENS) {
-                if (u.p0 < 0 || u.p0 >= (1 << 15) || u.p1 < -(1 << 15) || u.p1 >= (1 << 15)) { var_ok = false; break; }
-                prm = (u.p0 << 16) | (u.p1 & 0xFFFF);
-            } else prm = u.p0;
-            e[0] = ty;
-            e[1] = prm;
+            uint32_t &e = pairs[(size_t)j * 64 + t];
+            if (e != 0u) { var_ok = false; break; }  // two constraints on one pair
+            uint32_t prm = 0;
+            if (ty == U_QUEENS) {
+                if (u.p0 < 0 || u.p0 >= (1 << 13) || u.p1 < -(1 << 14) || u.p1 >= (1 << 14)) { var_ok = false; break; }
+                prm = ((uint32_t)u.p0 << 15) | ((uint32_t)u.p1 & 0x7FFFu);
+            } else {
+                const int32_t v = ty == U_TABLE ? u.p1 : u.p0;
+                if (v < -P28 || v >= P28) { var_ok = false; break; }
+                prm = (uint32_t)v & 0x0FFFFFFFu;
+            }
+            e = ((uint32_t)ty << 28) | prm;
         }
     }
-    if (!var_ok) pairs.assign(2, 0);
+    if (!var_ok) pairs.assign(1, 0u);
 
     // ---- pack and upload
     Packer pk;
@@ -481,7 +489,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     I.gcoef = (const int64_t *)(b8 + o_gc);
     I.unary = (const int32_t *)(b8 + o_un);
     I.feat_static = (const float *)(b8 + o_ft);
-    I.pairs = (const int2 *)(b8 + o_pairs);
+    I.pairs = (const uint32_t *)(b8 + o_pairs);
     I.var_ok = var_ok ? 1 : 0;
     I.unit_types = 0;
     for (const Unit &u : sorted) I.unit_types |= 1 << (u.tt >> 24);
@@ -553,7 +561,7 @@ int choose_layout(cubics_prob *const *probs, int B, int requested) {
     // segments once domains are wide
     cubics_ctx *ctx = probs[0]->ctx;
     auto it = ctx->tuned.find(probs[0]->bucket);
-    if (it != ctx->tuned.end()) return it->second;
+    if (it != ctx->tuned.end()) return it->second.layout;
     int dmax = 1;
     bool seg_ok = true, var_ok = true;
     for (int b = 0; b < B; ++b) {
@@ -561,14 +569,19 @@ int choose_layout(cubics_prob *const *probs, int B, int requested) {
         seg_ok &= probs[b]->dmax <= 64;
         var_ok &= probs[b]->dev.var_ok != 0;
     }
-    if (var_ok) return CUBICS_LAYOUT_VAR;
+    // registers pay off when the pair matrix and rows are staged in LDS (one
+    // instance); from HBM every dirty-variable step waits on a global load
+    if (var_ok && B == 1 && probs[0]->dev.blob_words * 4 <= 48 * 1024) return CUBICS_LAYOUT_VAR;
     return (seg_ok && dmax > 24) ? CUBICS_LAYOUT_SEG : CUBICS_LAYOUT_LANE;
 }
 
 }  // namespace
 
+// worker_div > 0: use the occupancy-limited worker count divided by it (the
+// autotuner's candidates); 0: the caller's count, else the autotuned one for
+// an AUTO layout, else the maximum.
 static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_limits *lims,
-                      cubics_result *results) {
+                      cubics_result *results, int worker_div = 0) {
     auto t0 = std::chrono::steady_clock::now();
     if (!probs || B < 1 || !results) return fail(CUBICS_EINVAL, "bad batch arguments");
     if (mode < 0 || mode > 2) return fail(CUBICS_EINVAL, "bad mode %d", mode);
@@ -624,7 +637,14 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     int bpc = 0;
     HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, variant));
     if (bpc < 1) bpc = 1;
-    int nworkers = L0.workers > 0 ? L0.workers : bpc * wpb * ctx->cu_count;
+    int div = 1;
+    if (worker_div > 0) {
+        div = worker_div;
+    } else if (L0.layout == CUBICS_LAYOUT_AUTO) {
+        auto it = ctx->tuned.find(probs[0]->bucket);
+        if (it != ctx->tuned.end()) div = it->second.div;
+    }
+    int nworkers = L0.workers > 0 && worker_div == 0 ? L0.workers : std::max(1, bpc * wpb * ctx->cu_count / div);
     const int blocks = (nworkers + wpb - 1) / wpb;
 
     // ---- buffers
@@ -784,7 +804,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
 }
 
 extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
-                               int64_t time_ms, int32_t *chosen) {
+                               int64_t time_ms, int32_t *chosen, int32_t *chosen_div, double *rates) {
     if (!probs || B < 1 || !probs[0] || time_ms < 1) return fail(CUBICS_EINVAL, "bad autotune arguments");
     bool seg_ok = true, var_ok = true;
     for (int b = 0; b < B; ++b) {
@@ -804,30 +824,37 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
     }
     lim[0].time_ms = time_ms;
     std::vector<cubics_result> res(B);
-    int best = CUBICS_LAYOUT_LANE;
+    if (rates)
+        for (int k = 0; k < 3 * CUBICS_AUTOTUNE_DIVS; ++k) rates[k] = 0.0;
+    cubics_ctx::Tuned best = {CUBICS_LAYOUT_LANE, 1};
     double best_rate = -1.0;
     int cands[3], nc = 0;
     cands[nc++] = CUBICS_LAYOUT_LANE;
     if (seg_ok) cands[nc++] = CUBICS_LAYOUT_SEG;
     if (var_ok) cands[nc++] = CUBICS_LAYOUT_VAR;
+    static const int divs[CUBICS_AUTOTUNE_DIVS] = {1, 2, 4};
     for (int ci = 0; ci < nc; ++ci) {
         lim[0].layout = cands[ci];
-        // a warm-up run, then the timed one
-        for (int rep = 0; rep < 2; ++rep) {
-            int rc = solve_impl(probs, B, mode == CUBICS_MODE_FIRST ? CUBICS_MODE_FIRST : CUBICS_MODE_COUNT,
-                                lim.data(), res.data());
-            if (rc) return rc;
-        }
-        uint64_t nodes = 0;
-        for (int b = 0; b < B; ++b) nodes += res[b].nodes;
-        const double rate = (double)nodes / std::max(res[0].kernel_ms, 1e-3);
-        if (rate > best_rate) {
-            best_rate = rate;
-            best = cands[ci];
+        for (int di = 0; di < CUBICS_AUTOTUNE_DIVS; ++di) {
+            // a warm-up run, then the timed one
+            for (int rep = 0; rep < 2; ++rep) {
+                int rc = solve_impl(probs, B, mode == CUBICS_MODE_FIRST ? CUBICS_MODE_FIRST : CUBICS_MODE_COUNT,
+                                    lim.data(), res.data(), divs[di]);
+                if (rc) return rc;
+            }
+            uint64_t nodes = 0;
+            for (int b = 0; b < B; ++b) nodes += res[b].nodes;
+            const double rate = (double)nodes / std::max(res[0].kernel_ms, 1e-3);
+            if (rates) rates[(cands[ci] - 1) * CUBICS_AUTOTUNE_DIVS + di] = rate;
+            if (rate > best_rate) {
+                best_rate = rate;
+                best = {cands[ci], divs[di]};
+            }
         }
     }
     probs[0]->ctx->tuned[probs[0]->bucket] = best;
-    if (chosen) *chosen = best;
+    if (chosen) *chosen = best.layout;
+    if (chosen_div) *chosen_div = best.div;
     return CUBICS_OK;
 }
 

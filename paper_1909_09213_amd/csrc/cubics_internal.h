@@ -15,9 +15,9 @@ enum UnitType : int32_t {
     U_QUEENS = 5,  // p0 = k, p1 = delta: a conflicts with b iff a - b - delta in {0, k, -k}
 };
 enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2 };
-// VAR layout pair entry {type, param}: TABLE param = word offset of the rows
-// indexed by the source value; NEQ / LT param = delta; QUEENS param =
-// k << 16 | (delta & 0xFFFF).
+// VAR layout pair entry, one word (type << 28) | param: TABLE param = word
+// offset of the rows indexed by the source value; NEQ / LT param = delta
+// (28-bit signed); QUEENS param = k << 15 | (delta & 0x7FFF).
 enum TaskKind : int32_t { K_ROOT = 0, K_NODE = 1, K_FRAME = 2 };
 
 // Binary unit (16 B).  tt = target var | type << 24.
@@ -55,7 +55,8 @@ struct InstDev {
     const int64_t *gcoef;
     const int32_t *unary;        // [n_unary][2] {var, row word offset}
     const float *feat_static;    // [n][4] static features for the learned policy
-    const int2 *pairs;           // [n][n] VAR layout: unit (t <- j) at [j*n + t] = {type, param}
+    const uint32_t *pairs;       // [n][64] VAR layout: unit (t <- j) at [j*64 + t], packed
+                                 // (type << 28) | param (28-bit signed; QUEENS: k << 15 | offset)
     const uint32_t *blob;        // start of the packed problem (all arrays above lie inside)
     uint32_t blob_words;         // its size in 32-bit words
     int32_t var_ok;              // VAR layout usable: n <= 64, one word per domain,

@@ -169,6 +169,11 @@ struct Counters {
     u64 nodes, fails, sols, steals, tasks;  // wave-uniform, flushed per instance
     u64 rev, bytes;                         // per lane, flushed per instance
     u64 stamp;                              // nodes of this worker, never reset
+    u64 ubytes;                             // wave-uniform bytes (trail copies)
+    // VAR layout, per lane, folded into rev / bytes at every poll and flush:
+    // revisions, revisions that changed the target, and the target popcounts
+    // of table revisions (bytes = 8 rev + 4 chg + 4 pop for one-word domains)
+    uint32_t vrev, vchg, vpop;
 };
 
 // ------------------------------------------------- binary unit revisions
@@ -853,9 +858,19 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
     }
 }
 
+// Fold the VAR layout's 32-bit per-lane counters into rev / bytes (done at
+// every poll, so they stay far below 2^32: at most 64 * 32 + 1 dirty-variable
+// steps per node, each one revision per lane of at most 32 popcount).
+DEV void fold_var(Counters &C) {
+    C.rev += C.vrev;
+    C.bytes += 8ull * C.vrev + 4ull * C.vchg + 4ull * C.vpop;
+    C.vrev = C.vchg = C.vpop = 0u;
+}
+
 template <int WM>
 DEV void flush(InstCtl *ctl, Counters &C, int lane) {
-    const u64 rev = wave_sumu64(C.rev), bytes = wave_sumu64(C.bytes);
+    fold_var(C);
+    const u64 rev = wave_sumu64(C.rev), bytes = wave_sumu64(C.bytes) + C.ubytes;
     if (lane == 0) {
         if (C.nodes) add_u64(&ctl->nodes, C.nodes);
         if (C.fails) add_u64(&ctl->fails, C.fails);
@@ -866,7 +881,7 @@ DEV void flush(InstCtl *ctl, Counters &C, int lane) {
         if (bytes) add_u64(&ctl->alg_bytes, bytes);
     }
     C.nodes = C.fails = C.sols = C.steals = C.tasks = 0;
-    C.rev = C.bytes = 0;
+    C.rev = C.bytes = C.ubytes = 0;
 }
 
 constexpr int POLL = 128;  // nodes between checks of stop flags and donation requests
@@ -1112,7 +1127,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                         if (lane + 64 * c < nw) snapc[c] = L.dom[lane + 64 * c];
                     snap_valid = true;
                 }
-                C.bytes += lane == 0 ? 4ull * nw : 0ull;
+                C.ubytes += 4ull * nw;
                 F.x = x;
                 F.depth = depth;
 #pragma unroll
@@ -1152,6 +1167,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                             float v = 0.f;
                             if (lane < POLICY_F) v = ((const float *)f)[16 + lane];
                             else if (lane == 5) v = (float)fdepth;
+                            else if (lane == 6) v = (float)b;
                             else if (lane == 7) v = log2f(1.f + (float)(C.stamp - st0));
                             P.trace_out[idx * TRACE_WORDS + lane] = v;
                         }
@@ -1189,7 +1205,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 } else {
                     for (int t = lane; t < nw; t += 64) L.dom[t] = f[FRAME_HDR + t];
                 }
-                C.bytes += lane == 0 ? 4ull * nw : 0ull;
+                C.ubytes += 4ull * nw;
                 wsync();
             }
             need_restore = true;
@@ -1299,28 +1315,49 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
 // register at once and feed the next dirty set through a ballot, so a node
 // needs no LDS traffic for domains or dirty sets.
 
-// Revision of target lane t against the broadcast source domain dj (pair
-// entry e = {type, param}); generic over the unit types.
-DEV uint32_t revise_var_generic(const InstDev &I, int2 e, uint32_t d, uint32_t dj) {
-    const int ty = e.x;
-    if (ty == U_TABLE) {
-        uint32_t acc = 0u, bits = dj;
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1;
-            acc |= I.rows[e.y + b];
+// Pair entries (one 32-bit word): type in bits 28..31, parameter in bits
+// 0..27 (signed); QUEENS packs k in bits 15..27 and the signed offset
+// lo_src - lo_tgt in bits 0..14.
+DEV int pair_type(uint32_t e) { return (int)(e >> 28); }
+DEV int pair_param(uint32_t e) { return (int)(e << 4) >> 4; }
+DEV int pair_qk(uint32_t e) { return (int)((e >> 15) & 0x1FFFu); }
+DEV int pair_qdl(uint32_t e) { return (int)(e << 17) >> 17; }
+
+// Support union of the rows of the source values in dj (uniform across the
+// wave): lowest and highest remaining bits, up to four row loads in flight,
+// with every bit operation on the scalar unit.
+DEV uint32_t table_union(const uint32_t *rows, uint32_t dj) {
+    uint32_t acc = 0u, bits = dj;
+    while (bits) {
+        const int a = __builtin_ctz(bits), b = 31 - __builtin_clz(bits);
+        bits &= ~((1u << a) | (1u << b));
+        if (bits) {
+            const int c = __builtin_ctz(bits), e = 31 - __builtin_clz(bits);
+            bits &= ~((1u << c) | (1u << e));
+            acc |= rows[a] | rows[b] | rows[c] | rows[e];
+        } else {
+            acc |= rows[a] | rows[b];
         }
-        return d & acc;
+    }
+    return acc;
+}
+
+// Revision of target lane t against the broadcast source domain dj (packed
+// pair entry e); generic over the unit types.
+DEV uint32_t revise_var_generic(const InstDev &I, uint32_t e, uint32_t d, uint32_t dj) {
+    const int ty = pair_type(e);
+    if (ty == U_TABLE) {
+        return d & table_union(I.rows + pair_param(e), dj);
     } else if (ty == U_NEQ) {
-        return __popc(dj) == 1 ? d & ~bit_in_word(__ffs(dj) - 1 + e.y, 0) : d;
+        return __popc(dj) == 1 ? d & ~bit_in_word(__ffs(dj) - 1 + pair_param(e), 0) : d;
     } else if (ty == U_LT_UB) {
-        return d & mask_le(31 - __clz(dj) + e.y - 1, 0);
+        return d & mask_le(31 - __clz(dj) + pair_param(e) - 1, 0);
     } else if (ty == U_LT_LB) {
-        return d & mask_ge(__ffs(dj) - 1 - e.y + 1, 0);
+        return d & mask_ge(__ffs(dj) - 1 - pair_param(e) + 1, 0);
     } else if (ty == U_QUEENS) {
         if (__popc(dj) > 3) return d;
-        const int kq = e.y >> 16;
-        const int dl = (int)(short)(e.y & 0xFFFF);
+        const int kq = pair_qk(e);
+        const int dl = pair_qdl(e);
         uint32_t uns = 0xFFFFFFFFu, bits = dj;
         while (bits) {
             const int b = __ffs(bits) - 1 + dl;
@@ -1332,48 +1369,32 @@ DEV uint32_t revise_var_generic(const InstDev &I, int2 e, uint32_t d, uint32_t d
     return d;
 }
 
-// Support union of the rows of the source values in dj (uniform across the
-// wave), four independent row loads in flight at a time.
-DEV uint32_t table_union(const uint32_t *rows, uint32_t dj) {
-    uint32_t acc = 0u, bits = dj;
-    while (bits) {
-        const int b0 = __ffs(bits) - 1;
-        bits &= bits - 1;
-        const int b1 = bits ? __ffs(bits) - 1 : b0;
-        bits &= bits - 1;
-        const int b2 = bits ? __ffs(bits) - 1 : b0;
-        bits &= bits - 1;
-        const int b3 = bits ? __ffs(bits) - 1 : b0;
-        bits &= bits - 1;
-        acc |= rows[b0] | rows[b1] | rows[b2] | rows[b3];
-    }
-    return acc;
-}
-
 // TYPES: 0 generic, 1 table units only, 2 queens units only (uniform choice).
+// The pair matrix has a row stride of 64, so every lane loads its entry
+// (lanes >= n read empty entries and hold empty domains).
 template <int TYPES>
 DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int lane) {
     const int n = I.n;
+    const u64 live = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
     while (cur) {
         u64 nxt = 0;
         int j = __ffsll((long long)cur) - 1;
-        int2 e = {0, 0};
-        if (lane < n) e = I.pairs[j * n + lane];
+        uint32_t e = I.pairs[j * 64 + lane];
         while (cur) {
             cur &= cur - 1;
             // prefetch the pair entry of the next dirty variable
             const int jn = cur ? __ffsll((long long)cur) - 1 : j;
-            int2 en = {0, 0};
-            if (lane < n) en = I.pairs[jn * n + lane];
+            const uint32_t en = I.pairs[jn * 64 + lane];
             const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)d, j);
             uint32_t nd = d;
-            if (e.x != 0) {
+            if (e != 0u) {
                 if (TYPES == 1) {
-                    nd = d & table_union(I.rows + e.y, dj);
+                    nd = d & table_union(I.rows + pair_param(e), dj);
+                    C.vpop += __popc(d);
                 } else if (TYPES == 2) {
                     if (__popc(dj) <= 3) {
-                        const int kq = e.y >> 16;
-                        const int dl = (int)(short)(e.y & 0xFFFF);
+                        const int kq = pair_qk(e);
+                        const int dl = pair_qdl(e);
                         uint32_t uns = 0xFFFFFFFFu, bits = dj;
                         while (bits) {
                             const int b = __ffs(bits) - 1 + dl;
@@ -1384,15 +1405,15 @@ DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, in
                     }
                 } else {
                     nd = revise_var_generic(I, e, d, dj);
+                    if (pair_type(e) == U_TABLE) C.vpop += __popc(d);
                 }
-                C.rev += 1;
-                C.bytes += rev_bytes(e.x, 1, __popc(d), nd != d);
+                C.vrev += 1u;
+                C.vchg += nd != d ? 1u : 0u;
             }
-            const bool ch = nd != d;
+            const u64 chm = __ballot(nd != d);
             d = nd;
-            const u64 chm = __ballot(ch);
             if (chm) {
-                if (__ballot(ch && nd == 0u)) return true;
+                if (__ballot(nd == 0u) & live) return true;
                 nxt |= chm;
             }
             j = jn;
@@ -1411,8 +1432,9 @@ DEV bool propagate_var(const InstDev &I, uint32_t &d, u64 cur, Counters &C, int 
 
 // first-fail over the register domains: 0 open (*bx), 1 solution, 2 failed
 DEV int node_test_var(int n, uint32_t d, int lane, int *bx) {
-    const int pop = lane < n ? __popc(d) : 0;
-    if (__ballot(lane < n && pop == 0)) return 2;
+    const int pop = __popc(d);  // 0 on lanes >= n
+    const u64 live = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    if (__ballot(pop == 0) & live) return 2;
     const u64 open = __ballot(pop >= 2);
     if (!open) return 1;
     for (int p = 2; p <= 32; ++p) {
@@ -1505,7 +1527,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 if (sp > 0 && lane == 0) trail[(size_t)(sp - 1) * FW + 4] = F.v[0];
                 uint32_t *f = trail + (size_t)sp * FW;
                 if (lane < n) f[FRAME_HDR + lane] = d;
-                C.bytes += lane == 0 ? 4ull * n : 0ull;
+                C.ubytes += 4ull * n;
                 snapc = d;
                 snap_valid = true;
                 F.x = x;
@@ -1540,7 +1562,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                     snap_valid = true;
                 }
                 d = snapc;
-                C.bytes += lane == 0 ? 4ull * n : 0ull;
+                C.ubytes += 4ull * n;
             }
             need_restore = true;
             if (lane == F.x) d = 1u << vi;
@@ -1567,6 +1589,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
             }
         }
         if (++since_poll >= POLL) {
+            fold_var(C);
             since_poll = 0;
             int stop = 0, idle = 0;
             u64 qlen = 0;
@@ -1641,7 +1664,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
     I.gcoef = (const int64_t *)(t0 + ((const char *)g.gcoef - b0));
     I.unary = (const int32_t *)(t0 + ((const char *)g.unary - b0));
     I.feat_static = (const float *)(t0 + ((const char *)g.feat_static - b0));
-    I.pairs = (const int2 *)(t0 + ((const char *)g.pairs - b0));
+    I.pairs = (const uint32_t *)(t0 + ((const char *)g.pairs - b0));
     I.blob = tab;
     return I;
 }
@@ -1684,7 +1707,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     L.scr = base + off;
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
     const long long t_start = (long long)wall_clock64();
-    Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
+    Counters C = {};
     bool idle = false;
     // Idle workers back off exponentially (up to ~27 us between polls): with
     // thousands of waves polling the same queue words, the polls themselves
@@ -1815,7 +1838,7 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
         for (int k = 0; k < W; ++k) atomicAnd(&L.dom[v * W + k], I.rows[o + k]);
     }
     wsync();
-    Counters C = {0, 0, 0, 0, 0, 0, 0, 0};
+    Counters C = {};
     int bx = 0;
     bool fail = node_test<WM>(I, L, lane, &bx) == 2;
     if (!fail) {

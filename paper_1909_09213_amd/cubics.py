@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libcubics.so")
 
 MODE_FIRST, MODE_ALL, MODE_COUNT = 0, 1, 2
 LAYOUT_AUTO, LAYOUT_LANE, LAYOUT_SEG, LAYOUT_VAR = 0, 1, 2, 3
+AUTOTUNE_DIVS = 3  # worker counts the autotuner tries: the maximum divided by 1, 2, 4
+AUTOTUNE_DIV_VALUES = (1, 2, 4)
 BRANCH_FIRST_FAIL, BRANCH_LEARNED = 0, 1
 VERDICTS = {0: "SAT", 1: "UNSAT", 2: "LIMIT", 3: "CANCELLED"}
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED"}
@@ -100,7 +102,8 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
-    lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32)]
+    lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32),
+                                    ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.cubics_policy_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.cubics_policy_free.argtypes = [vp]
     lib.cubics_policy_free.restype = None
@@ -218,8 +221,10 @@ class Context:
         return Problem(self, h, inst)
 
     # ------------------------------------------------------------ autotune
-    def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, **kw) -> int:
-        """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG, 3 VAR)."""
+    def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, rates: bool = False, **kw):
+        """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG, 3 VAR);
+        with rates=True, (layout, worker divisor, {(layout, divisor): nodes
+        per ms}) for every pair tried."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()
@@ -229,8 +234,13 @@ class Context:
             L.split_target = kw.get("split_target", 0)
             L.max_nodes = kw.get("max_nodes", 0)
             lims[b] = L
-        chosen = ctypes.c_int32()
-        _check(_lib.cubics_autotune(arr, B, mode, lims, time_ms, ctypes.byref(chosen)))
+        chosen, div = ctypes.c_int32(), ctypes.c_int32()
+        rt = (ctypes.c_double * (3 * AUTOTUNE_DIVS))()
+        _check(_lib.cubics_autotune(arr, B, mode, lims, time_ms, ctypes.byref(chosen), ctypes.byref(div), rt))
+        if rates:
+            table = {(k // AUTOTUNE_DIVS + 1, AUTOTUNE_DIV_VALUES[k % AUTOTUNE_DIVS]): rt[k]
+                     for k in range(3 * AUTOTUNE_DIVS) if rt[k] > 0}
+            return chosen.value, div.value, table
         return chosen.value
 
     # ---------------------------------------------------------------- root

@@ -5,9 +5,17 @@
    searched by one worker and its size is exact), with a fraction of the
    branchings exploring among the 4 smallest domains.  Every completed
    subtree below a branching yields a record (5 features of the branching
-   variable, depth, label = log2(1 + nodes below)).
-2. train(): full-batch Adam on the GPU with the library's own forward /
-   backward / optimizer kernels (bf16 MFMA forward, fp32 master weights).
+   variable, depth, instance, label = log2(1 + nodes below)).
+2. train(): the labels are centred per (instance, depth) - the mean label of
+   the group is subtracted - so that the network learns how the choice of
+   variable moves the subtree size at a node, not how instance and depth
+   do (raw labels mostly measure those: first-fail branches on high-degree
+   variables near the root, where subtrees are large, which teaches the
+   opposite of the degree preference that shrinks the tree).  All
+   candidates at a node share instance and depth, so the argmin is
+   unchanged by the centring.  Then full-batch Adam on the GPU with the
+   library's own forward / backward / optimizer kernels (bf16 MFMA forward,
+   fp32 master weights).
 3. evaluate(): the same held-out instances under first-fail and under the
    learned policy; verdicts and counts must agree, nodes and time compared.
 
@@ -62,7 +70,9 @@ def collect(ctx: cb.Context, insts, cap: int = 4_000_000, explore_pm: int = 250,
         res = ctx.solve_batch(probs, cb.MODE_COUNT, donate=False, max_nodes=max_nodes,
                               trace=buf, explore_pm=explore_pm, seed=seed + c0)
         n = min(res[0].traces, buf.shape[0])
-        out.append(buf[:n].clone())
+        part_rec = buf[:n].clone()
+        part_rec[:, 6] += c0  # instance index within the whole list
+        out.append(part_rec)
         total += n
         for p in probs:
             p.free()
@@ -71,9 +81,26 @@ def collect(ctx: cb.Context, insts, cap: int = 4_000_000, explore_pm: int = 250,
     return torch.cat(out, 0) if out else torch.zeros((0, 8), device=ctx.torch_device)
 
 
+def centre_labels(rec):
+    """Copy of the records with column 7 replaced by the label minus the mean
+    label of its (instance, depth) group."""
+    import torch
+    key = rec[:, 6].to(torch.int64) * 65536 + rec[:, 5].to(torch.int64)
+    _, inv = torch.unique(key, return_inverse=True)
+    g = int(inv.max().item()) + 1 if inv.numel() else 0
+    s = torch.zeros(g, dtype=torch.float64, device=rec.device).index_add_(0, inv, rec[:, 7].double())
+    c = torch.zeros(g, dtype=torch.float64, device=rec.device).index_add_(
+        0, inv, torch.ones_like(rec[:, 7], dtype=torch.float64))
+    out = rec.clone()
+    out[:, 7] = (rec[:, 7].double() - (s / c)[inv]).float()
+    return out
+
+
 def train(ctx: cb.Context, rec, steps: int = 300, lr: float = 3e-3, seed: int = 0,
-          theta=None, log_every: int = 0):
+          theta=None, log_every: int = 0, centre: bool = True):
     """Train the policy on trace records with full-batch Adam on the GPU."""
+    if centre:
+        rec = centre_labels(rec)
     pol = cb.Policy(ctx, init_theta(seed) if theta is None else theta)
     losses = []
     for s in range(1, steps + 1):
@@ -86,13 +113,15 @@ def train(ctx: cb.Context, rec, steps: int = 300, lr: float = 3e-3, seed: int = 
 
 def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_nodes: int = 0):
     """Solve every instance under first-fail and under the policy (one batched
-    launch each).  Returns per-policy totals and per-instance results."""
+    launch each, both in the LANE layout, which the learned path uses).
+    Returns per-policy totals and per-instance results."""
     probs = [ctx.load(x) for x in insts]
     out = {}
     for name, br, pol in (("first_fail", cb.BRANCH_FIRST_FAIL, None),
                           ("learned", cb.BRANCH_LEARNED, policy)):
         t0 = time.perf_counter()
-        res = ctx.solve_batch(probs, mode, branching=br, policy=pol, max_nodes=max_nodes)
+        res = ctx.solve_batch(probs, mode, branching=br, policy=pol, max_nodes=max_nodes,
+                              layout=cb.LAYOUT_LANE)
         dt = time.perf_counter() - t0
         out[name] = {"results": res, "nodes": sum(r.nodes for r in res),
                      "kernel_ms": res[0].kernel_ms, "wall_s": dt}
@@ -126,12 +155,16 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
             raise AssertionError(f"policy changed the count of eval instance {i}")
     nodes_ff = sum(ff[i].nodes for i in both)
     nodes_le = sum(le[i].nodes for i in both)
+    ratios = np.array([le[i].nodes / ff[i].nodes for i in both], dtype=np.float64)
     report = {
         "train_instances": n_train, "eval_instances": n_eval, "eval_resolved_by_both": len(both),
         "trace_records": int(rec.shape[0]), "train_steps": steps,
         "loss_first": losses[0], "loss_last": losses[-1],
         "nodes_first_fail": nodes_ff, "nodes_learned": nodes_le,
         "node_ratio_learned_over_ff": nodes_le / max(nodes_ff, 1),
+        "node_ratio_geomean": float(np.exp(np.mean(np.log(ratios)))) if len(both) else None,
+        "instances_fewer_nodes": int((ratios < 1).sum()),
+        "instances_more_nodes": int((ratios > 1).sum()),
         "time_to_all_ms_first_fail": ev["first_fail"]["kernel_ms"],
         "time_to_all_ms_learned": ev["learned"]["kernel_ms"],
         "time_ratio_learned_over_ff": ev["learned"]["kernel_ms"] / max(ev["first_fail"]["kernel_ms"], 1e-9),

@@ -191,8 +191,10 @@ def test_graph_replay_matches_eager(ctx, cb):
 def test_autotune_then_auto_layout(ctx, cb):
     inst = cspgen.rb(0).fix({0: 3, 1: 5, 2: 7})
     p = ctx.load(inst)
-    chosen = ctx.autotune([p], cb.MODE_COUNT, time_ms=30)
-    assert chosen in (1, 2)
+    chosen, div, rates = ctx.autotune([p], cb.MODE_COUNT, time_ms=30, rates=True)
+    # n = 40 <= 64, one word per domain: every layout admitted
+    assert {lay for lay, _ in rates} == {1, 2, 3}
+    assert rates[(chosen, div)] == max(rates.values())
     ref = oracle.solve(inst, oracle.MODE_COUNT)
     r = ctx.solve(p, cb.MODE_COUNT)
     assert (r.count, r.nodes) == (ref.count, ref.nodes)
