@@ -242,6 +242,15 @@ int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cu
  * accumulation on the matrix cores; theta stays the fp32 master copy.  The
  * policy never changes what propagation computes, only the search order. */
 
+/* The 5 policy features of every variable at a search node whose domains are
+   dom_bits (host, n * W words as cubics_root returns them; NULL = the
+   problem's initial domains) at the given depth (number of branchings above
+   it, >= 0), with no failures counted: |D_i| / d_i, static degree / (n - 1),
+   mean static tightness of the variable's constraints, depth / n,
+   log2(1 + failures) = 0.  out (host, n * 5 floats) receives them, row i =
+   variable i.  The values are those the branching step computes. */
+int cubics_features(cubics_prob *prob, const uint32_t *dom_bits, int32_t depth, float *out);
+
 /* Upload theta (copied) and zero the optimizer state. */
 int cubics_policy_create(cubics_ctx *ctx, const float *theta, cubics_policy **out);
 void cubics_policy_free(cubics_policy *policy);

@@ -24,6 +24,8 @@ int search_variant(int feat, bool glob, bool seg, bool var);
 hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *failed,
                        unsigned long long *revs, size_t lds, hipStream_t st);
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
+hipError_t launch_features(const InstDev *inst, const uint32_t *dom, int depth, float *out, int n,
+                           hipStream_t st);
 hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant);
 }  // namespace cubics
 
@@ -867,6 +869,29 @@ extern "C" int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits
 extern "C" int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
                                   cubics_result *results) {
     return solve_impl(probs, B, mode, limits, results);
+}
+
+extern "C" int cubics_features(cubics_prob *p, const uint32_t *dom_bits, int32_t depth, float *out) {
+    if (!p || !out) return fail(CUBICS_EINVAL, "NULL argument");
+    if (depth < 0) return fail(CUBICS_EINVAL, "negative depth");
+    cubics_ctx *ctx = p->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t n = (size_t)std::max(p->n, 0), nw = std::max<size_t>(n * p->W, 1);
+    int rc;
+    if ((rc = ctx->inst.ensure(sizeof(InstDev)))) return rc;
+    if ((rc = ctx->rootout.ensure(nw * 4 + n * POLICY_F * 4 + 64))) return rc;
+    if (n == 0) return CUBICS_OK;
+    uint32_t *ddom = (uint32_t *)ctx->rootout.p;
+    float *dout = (float *)((char *)ctx->rootout.p + nw * 4);
+    HIPCHK(hipMemcpyAsync(ctx->inst.p, &p->dev, sizeof(InstDev), hipMemcpyHostToDevice, ctx->stream));
+    if (dom_bits)
+        HIPCHK(hipMemcpyAsync(ddom, dom_bits, n * p->W * 4, hipMemcpyHostToDevice, ctx->stream));
+    else
+        HIPCHK(hipMemcpyAsync(ddom, p->dev.dom0, n * p->W * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(launch_features((const InstDev *)ctx->inst.p, ddom, depth, dout, (int)n, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, dout, n * POLICY_F * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return CUBICS_OK;
 }
 
 extern "C" int cubics_root(cubics_prob *p, int32_t layout, uint32_t *out_bits, int32_t *failed) {

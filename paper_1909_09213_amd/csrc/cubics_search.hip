@@ -891,13 +891,13 @@ constexpr int POLL = 128;  // nodes between checks of stop flags and donation re
 
 // Feature k (0..4) of variable i at a node of depth `depth`: domain fraction,
 // static degree / (n-1), mean static tightness, depth / n, log2(1 + fails).
-DEV float var_feature(const InstDev &I, const Lds &L, int i, int k, int depth, int pop) {
+DEV float var_feature(const InstDev &I, int i, int k, int depth, int pop, uint32_t fails) {
     switch (k) {
     case 0: return (float)pop * I.feat_static[4 * i + 2];
     case 1: return I.feat_static[4 * i + 0];
     case 2: return I.feat_static[4 * i + 1];
     case 3: return (float)depth / (float)(I.n > 0 ? I.n : 1);
-    default: return log2f(1.f + (float)L.fails[i]);
+    default: return log2f(1.f + (float)fails);
     }
 }
 
@@ -945,7 +945,7 @@ DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, in
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = 4 * kq + j;
-            const float f = (i < n && k < POLICY_F) ? var_feature(I, L, i, k, depth, pop) : 0.f;
+            const float f = (i < n && k < POLICY_F) ? var_feature(I, i, k, depth, pop, L.fails[i]) : 0.f;
             xT[j] = (short)f2bf(f);
         }
         const f32x4 acc = mlp_tile<true>(pol, xT, lane, nullptr);
@@ -1135,7 +1135,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 frame_store_meta<WM>(f, F, lane);
                 if (tracing) {
                     const int px = var_pop<WM>(I, L, x);
-                    if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, L, x, lane, depth, px);
+                    if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, x, lane, depth, px, L.fails[x]);
                     if (lane == 0) {
                         f[24] = (uint32_t)C.stamp;
                         f[25] = (uint32_t)(C.stamp >> 32);
@@ -1772,6 +1772,18 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
 }
 
 #if CUBICS_ONLY_WM == 1
+// Policy features of every variable at a given node (domains dom[n][W],
+// depth), with no failures counted: the same values the branching step and
+// the trace records use.
+__global__ void features_kernel(const InstDev *inst, const uint32_t *dom, int depth, float *out) {
+    const InstDev &I = *inst;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < I.n; i += gridDim.x * blockDim.x) {
+        int pop = 0;
+        for (int k = 0; k < I.W; ++k) pop += __popc(dom[i * I.W + k]);
+        for (int k = 0; k < POLICY_F; ++k) out[i * POLICY_F + k] = var_feature(I, i, k, depth, pop, 0u);
+    }
+}
+
 // Reset the queue and seed it with one ROOT task per instance.
 __global__ void init_kernel(SearchParams P) {
     const uint32_t cap = P.qmask + 1u;
@@ -1934,6 +1946,12 @@ hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *
 }
 hipError_t launch_init(const SearchParams &P, hipStream_t st) {
     hipLaunchKernelGGL(init_kernel, dim3(256), dim3(256), 0, st, P);
+    return hipGetLastError();
+}
+hipError_t launch_features(const InstDev *inst, const uint32_t *dom, int depth, float *out, int n,
+                           hipStream_t st) {
+    const int blocks = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
+    hipLaunchKernelGGL(features_kernel, dim3(blocks), dim3(256), 0, st, inst, dom, depth, out);
     return hipGetLastError();
 }
 hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant) {

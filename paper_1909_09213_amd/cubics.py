@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_free.restype = None
     lib.cubics_prob_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
+    lib.cubics_features.argtypes = [vp, vp, i32, vp]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32),
@@ -113,7 +114,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_mlp_grad.argtypes = [vp, vp, i32, vp, i32, i64, vp, vp]
     lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
-              "cubics_root", "cubics_solve", "cubics_solve_batch", "cubics_autotune", "cubics_policy_create",
+              "cubics_root", "cubics_features", "cubics_solve", "cubics_solve_batch", "cubics_autotune", "cubics_policy_create",
               "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
               "cubics_mlp_train_step"):
         getattr(lib, f).restype = ctypes.c_int
@@ -244,11 +245,27 @@ class Context:
         return chosen.value
 
     # ---------------------------------------------------------------- root
-    def root(self, prob: Problem, layout: int = LAYOUT_AUTO):
+    def root(self, prob: Problem, layout: int = LAYOUT_AUTO, device_words: bool = False):
+        """cubics_root: (failed, domains [n, W]); W = the caller's words per
+        domain, or the device's (which may be wider) with device_words."""
         out = np.zeros((max(prob.n, 1), prob.W), dtype=np.uint32)
         failed = ctypes.c_int32()
         _check(_lib.cubics_root(prob.handle, layout, out.ctypes.data, ctypes.byref(failed)))
-        return bool(failed.value), out[:prob.n, :prob.W_in].copy()
+        return bool(failed.value), out[:prob.n, :(prob.W if device_words else prob.W_in)].copy()
+
+    def features(self, prob: Problem, dom=None, depth: int = 0) -> np.ndarray:
+        """cubics_features: [n, 5] policy features at a node with domains dom
+        ([n, W] device words, as root(..., device_words=True) returns; None =
+        the initial domains) and the given depth."""
+        out = np.zeros((max(prob.n, 1), 5), dtype=np.float32)
+        ptr = None
+        if dom is not None:
+            dom = np.ascontiguousarray(dom, dtype=np.uint32)
+            if dom.shape != (prob.n, prob.W):
+                raise ValueError(f"dom must have shape {(prob.n, prob.W)}")
+            ptr = dom.ctypes.data
+        _check(_lib.cubics_features(prob.handle, ptr, depth, out.ctypes.data))
+        return out[:prob.n].copy()
 
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,

@@ -1,18 +1,25 @@
-"""Learned variable ordering: trace collection, GPU training, evaluation.
+"""Learned variable ordering: search traces, GPU training, evaluation.
 
-1. collect(): solve instances with the plain first-fail solver in count
-   mode, one instance per worker (no donation, no split, so every subtree is
-   searched by one worker and its size is exact), with a fraction of the
-   branchings exploring among the 4 smallest domains.  Every completed
-   subtree below a branching yields a record (5 features of the branching
-   variable, depth, instance, label = log2(1 + nodes below)).
-2. train(): the labels are centred per (instance, depth) - the mean label of
-   the group is subtracted - so that the network learns how the choice of
-   variable moves the subtree size at a node, not how instance and depth
-   do (raw labels mostly measure those: first-fail branches on high-degree
-   variables near the root, where subtrees are large, which teaches the
-   opposite of the degree preference that shrinks the tree).  All
-   candidates at a node share instance and depth, so the argmin is
+1. Traces of the plain solver.  Two kinds, both produced by the library:
+   - collect(): count-mode solves, one instance per worker (no donation, no
+     split, so every subtree is searched by one worker and its size is
+     exact), a fraction of the branchings exploring among the 4 smallest
+     domains; every completed subtree below a branching yields a record (5
+     features of the branching variable, depth, instance, label =
+     log2(1 + nodes below)).  These are observational: each node has one
+     branching, and a regression on them learns what instance and depth do
+     to subtree sizes (first-fail branches on high-degree variables near
+     the root, where subtrees are large, so degree comes out as predicting
+     LARGER subtrees - the opposite of what shrinks the tree).
+   - sample_nodes() + sibling_records(): at sampled search nodes, the
+     subtree below branching on EACH of several candidate variables is
+     counted by the plain solver (every child x = v solved exhaustively in
+     one batched launch).  Records of one node differ only in the choice of
+     variable; this is what the policy is trained on.
+2. train(): labels centred per group of column 6 / column 5 (node id and
+   depth for sibling records; instance and depth for collect()'s), so the
+   network learns how the choice of variable moves the subtree size at a
+   node; every candidate at a node shares the group, so the argmin is
    unchanged by the centring.  Then full-batch Adam on the GPU with the
    library's own forward / backward / optimizer kernels (bf16 MFMA forward,
    fp32 master weights).
@@ -81,6 +88,106 @@ def collect(ctx: cb.Context, insts, cap: int = 4_000_000, explore_pm: int = 250,
     return torch.cat(out, 0) if out else torch.zeros((0, 8), device=ctx.torch_device)
 
 
+def sample_nodes(ctx: cb.Context, insts, seed: int = 0):
+    """One search node per instance: a random descent from the root (the
+    branching variable by first-fail on half of the steps, else uniform among
+    the unassigned; the value uniform), propagated on the GPU after every
+    branching, to a depth drawn uniformly in [1, n/2]; a descent that fails
+    stops at its last consistent node.  Returns (index, depth, domains) with
+    the fixpoint domains of the node ([n, W] words)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, inst in enumerate(insts):
+        target = int(rng.integers(1, max(2, inst.n // 2 + 1)))
+        prob = ctx.load(inst)
+        failed, dom = ctx.root(prob, device_words=True)
+        prob.free()
+        if failed:
+            continue
+        depth = 0
+        while depth < target:
+            pops = np.array([sum(bin(int(w)).count("1") for w in row) for row in dom])
+            free = np.flatnonzero(pops >= 2)
+            if free.size == 0:
+                break
+            if rng.integers(0, 2) == 0:
+                x = int(free[np.lexsort((free, pops[free]))[0]])
+            else:
+                x = int(rng.choice(free))
+            vals = [32 * w + b for w in range(dom.shape[1]) for b in range(32) if (int(dom[x, w]) >> b) & 1]
+            a = int(rng.choice(vals))
+            init = dom.copy()
+            init[x] = 0
+            init[x, a // 32] = np.uint32(1 << (a % 32))
+            prob = ctx.load(inst.with_init(init))
+            failed, child = ctx.root(prob, device_words=True)
+            prob.free()
+            if failed:
+                break
+            dom, depth = child, depth + 1
+        if depth >= 1:
+            out.append((k, depth, dom))
+    return out
+
+
+def sibling_records(ctx: cb.Context, insts, nodes, n_small: int = 6, n_other: int = 2,
+                    max_nodes: int = 2_000_000, seed: int = 0, chunk: int = 4096):
+    """Subtree sizes of alternative branchings at the same node, from the
+    plain solver: at each sampled node, for each candidate variable x (the
+    n_small smallest domains and n_other others, uniformly), every child
+    x = v is counted exhaustively in one batched launch; the subtree below
+    branching on x holds sum_v nodes(child v).  Records [N, 8] (torch,
+    device): features of x at the node, depth, node id, label
+    log2(1 + subtree size).  Nodes with a child over max_nodes are dropped."""
+    import torch
+    rng = np.random.default_rng(seed)
+    jobs = []  # (node id, x, child init)
+    feats = {}
+    for nid, (k, depth, dom) in enumerate(nodes):
+        inst = insts[k]
+        pops = np.array([sum(bin(int(w)).count("1") for w in row) for row in dom])
+        free = np.flatnonzero(pops >= 2)
+        if free.size < 2:
+            continue
+        order = free[np.lexsort((free, pops[free]))]
+        cands = list(order[:n_small])
+        rest = order[n_small:]
+        if rest.size:
+            cands += list(rng.choice(rest, size=min(n_other, rest.size), replace=False))
+        prob = ctx.load(inst.with_init(dom[:, :inst.W]))
+        feats[nid] = (ctx.features(prob, dom, depth), depth)
+        prob.free()
+        for x in cands:
+            x = int(x)
+            for w in range(dom.shape[1]):
+                for b in range(32):
+                    if (int(dom[x, w]) >> b) & 1:
+                        init = dom[:, :inst.W].copy()
+                        init[x] = 0
+                        init[x, w] = np.uint32(1 << b)
+                        jobs.append((nid, x, inst, init))
+    size = {}
+    over = set()
+    for c0 in range(0, len(jobs), chunk):
+        part = jobs[c0:c0 + chunk]
+        probs = [ctx.load(inst.with_init(init)) for _, _, inst, init in part]
+        res = ctx.solve_batch(probs, cb.MODE_COUNT, max_nodes=max_nodes)
+        for (nid, x, _, _), r in zip(part, res):
+            if r.verdict == "LIMIT":
+                over.add(nid)
+            size[(nid, x)] = size.get((nid, x), 0) + r.nodes
+        for p in probs:
+            p.free()
+    rows = []
+    for (nid, x), sz in size.items():
+        if nid in over:
+            continue
+        f, depth = feats[nid]
+        rows.append(list(f[x]) + [float(depth), float(nid), float(np.log2(1.0 + sz))])
+    rec = np.asarray(rows, dtype=np.float32).reshape(-1, 8)
+    return torch.from_numpy(rec).to(ctx.torch_device)
+
+
 def centre_labels(rec):
     """Copy of the records with column 7 replaced by the label minus the mean
     label of its (instance, depth) group."""
@@ -101,7 +208,14 @@ def train(ctx: cb.Context, rec, steps: int = 300, lr: float = 3e-3, seed: int = 
     """Train the policy on trace records with full-batch Adam on the GPU."""
     if centre:
         rec = centre_labels(rec)
-    pol = cb.Policy(ctx, init_theta(seed) if theta is None else theta)
+    if theta is None:
+        theta = init_theta(seed)
+        # a feature that is constant in the data gets no gradient: start it
+        # (and keep it) at zero weight instead of a random one
+        const = (rec[:, :F].max(0).values - rec[:, :F].min(0).values).cpu().numpy() == 0
+        W1 = theta[:H * F].reshape(H, F)
+        W1[:, const] = 0.0
+    pol = cb.Policy(ctx, theta)
     losses = []
     for s in range(1, steps + 1):
         loss = pol.train_step(rec, lr, s)
@@ -130,17 +244,20 @@ def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_node
     return out
 
 
-def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps: int = 300,
-               lr: float = 1e-2, explore_pm: int = 250, eval_max_nodes: int = 50_000_000,
+def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps: int = 1500,
+               lr: float = 1e-2, eval_max_nodes: int = 50_000_000,
                train_base: int = cspgen.SEED_TRAIN, eval_base: int = cspgen.SEED_EVAL):
-    """Train on traces from n_train seeded instances, evaluate time-to-all
-    (count mode) on n_eval held-out seeds under first-fail and the policy.
-    Returns a report dict; raises if any verdict or count differs."""
+    """Sample one node from each of n_train seeded instances, label the
+    alternative branchings there with the plain solver's subtree sizes,
+    train, and evaluate time-to-all (count mode) on n_eval held-out seeds
+    under first-fail and the policy.  Returns a report dict; raises if any
+    verdict or count differs."""
     t0 = time.perf_counter()
     train_insts = instances(train_base, n_train)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    rec = collect(ctx, train_insts, explore_pm=explore_pm)
+    nodes = sample_nodes(ctx, train_insts, seed=train_base)
+    rec = sibling_records(ctx, train_insts, nodes, seed=train_base)
     t_collect = time.perf_counter() - t0
     del train_insts
     t0 = time.perf_counter()
@@ -157,8 +274,9 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
     nodes_le = sum(le[i].nodes for i in both)
     ratios = np.array([le[i].nodes / ff[i].nodes for i in both], dtype=np.float64)
     report = {
-        "train_instances": n_train, "eval_instances": n_eval, "eval_resolved_by_both": len(both),
-        "trace_records": int(rec.shape[0]), "train_steps": steps,
+        "train_instances": n_train, "train_nodes": len(nodes), "eval_instances": n_eval,
+        "eval_resolved_by_both": len(both),
+        "records": int(rec.shape[0]), "train_steps": steps,
         "loss_first": losses[0], "loss_last": losses[-1],
         "nodes_first_fail": nodes_ff, "nodes_learned": nodes_le,
         "node_ratio_learned_over_ff": nodes_le / max(nodes_ff, 1),
@@ -168,7 +286,7 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
         "time_to_all_ms_first_fail": ev["first_fail"]["kernel_ms"],
         "time_to_all_ms_learned": ev["learned"]["kernel_ms"],
         "time_ratio_learned_over_ff": ev["learned"]["kernel_ms"] / max(ev["first_fail"]["kernel_ms"], 1e-9),
-        "seconds": {"generate": t_gen, "collect": t_collect, "train": t_train},
+        "seconds": {"generate": t_gen, "label": t_collect, "train": t_train},
         "theta": pol.get().tolist(),
     }
     return report
@@ -181,7 +299,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--train", type=int, default=20000)
     ap.add_argument("--eval", type=int, default=4096)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=1500)
     args = ap.parse_args()
     ctx = cb.Context(0)
     rep = experiment(ctx, n_train=args.train, n_eval=args.eval, steps=args.steps)

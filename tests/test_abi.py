@@ -44,5 +44,9 @@ def test_null_arguments_are_rejected_without_gpu_work():
     assert b"ctx" in lib.cubics_last_error()
     lib.cubics_solve.restype = ctypes.c_int
     assert lib.cubics_solve(None, 0, None, None) == -1
+    lib.cubics_features.restype = ctypes.c_int
+    assert lib.cubics_features(None, None, 0, None) == -1
+    lib.cubics_autotune.restype = ctypes.c_int
+    assert lib.cubics_autotune(None, 0, 0, None, ctypes.c_int64(1), None, None, None) == -1
     lib.cubics_free(None)
     lib.cubics_destroy(None)

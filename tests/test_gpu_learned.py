@@ -119,5 +119,48 @@ def test_trace_collection_and_training(ctx, cb):
     r = rec.cpu().numpy()
     assert np.all(r[:, 7] >= 0) and np.all(np.isfinite(r))
     assert np.all((r[:, 0] > 0) & (r[:, 0] <= 1))
+    assert np.all((r[:, 6] == np.floor(r[:, 6])) & (r[:, 6] >= 0) & (r[:, 6] < len(insts)))
+    # labels centred per (instance, depth): zero mean in every group
+    c = learn.centre_labels(rec).cpu().numpy()
+    key = r[:, 6].astype(np.int64) * 65536 + r[:, 5].astype(np.int64)
+    sums = np.bincount(np.unique(key, return_inverse=True)[1], weights=c[:, 7])
+    assert np.max(np.abs(sums)) < 1e-2 * max(1.0, float(np.abs(c[:, 7]).sum()) / len(sums))
     pol, losses = learn.train(ctx, rec, steps=150, lr=1e-2)
-    assert losses[-1] < 0.7 * losses[0]
+    # the network explains part of the centred labels' variance (the loss of
+    # the best constant predictor, 0)
+    var0 = float(np.mean(c[:, 7].astype(np.float64) ** 2))
+    print(f"loss {losses[0]:.3f} -> {losses[-1]:.3f}, constant predictor {var0:.3f}", file=sys.stderr)
+    assert losses[-1] < losses[0] and losses[-1] < 0.98 * var0
+
+
+def test_features_match_their_definition(ctx, cb):
+    """cubics_features against the features written out from the instance:
+    |D_i| / d_i, (number of constraints on i) / (n - 1), mean over i's
+    tables of the forbidden fraction, depth / n, log2(1 + 0)."""
+    inst = cspgen.rb_sweep(7, base=321, nlo=14, nhi=18, dlo=5, dhi=9, plo=300, phi=500,
+                           tlo=300, thi=450)
+    n = inst.n
+    deg = np.zeros(n)
+    tsum = np.zeros(n)
+    for c in range(inst.m):
+        i, j = (int(v) for v in inst.scope(c))
+        di, dj = int(inst.dsize[i]), int(inst.dsize[j])
+        bits = np.unpackbits(inst.tab(c).view(np.uint8), bitorder="little").reshape(di, -1)[:, :dj]
+        t = 1.0 - bits.sum() / (di * dj)
+        for v in (i, j):
+            deg[v] += 1
+            tsum[v] += t
+    sub = inst.fix({0: int(inst.lo[0]), 3: int(inst.lo[3]) + 1})
+    p = ctx.load(sub)
+    failed, dom = ctx.root(p, device_words=True)
+    assert not failed
+    got = ctx.features(p, dom, depth=2)
+    pop = np.array([sum(bin(int(w)).count("1") for w in row) for row in dom])
+    want = np.stack([pop / inst.dsize, deg / (n - 1), np.where(deg > 0, tsum / np.maximum(deg, 1), 0),
+                     np.full(n, 2 / n), np.zeros(n)], axis=1)
+    assert np.allclose(got, want, rtol=1e-6, atol=1e-7), np.max(np.abs(got - want))
+    # NULL domains = the initial ones
+    got0 = ctx.features(p, None, depth=0)
+    pop0 = np.array([sum(bin(int(w)).count("1") for w in row) for row in sub.full_init()])
+    assert np.allclose(got0[:, 0], pop0 / inst.dsize, rtol=1e-6)
+    assert np.all(got0[:, 3] == 0)
