@@ -19,8 +19,11 @@ instance once.
 
 The JSON line reports nodes/s (value), revisions/s, the roofline of the
 search kernel (algorithmic domain/table/trail bytes over the kernel time
-measured with HIP events on the library's stream), and the CPU oracle timed
-on a bounded sample of the same workload.
+measured with HIP events on the library's stream), the learned-vs-first-fail
+leg (untimed: a policy trained on the plain solver's sibling subtree sizes
+at nodes of --learned-train seeded instances, then time-to-all-solutions and
+node counts of --learned-eval held-out instances under both orderings), and
+the CPU oracle timed on a bounded sample of the RB workload.
 """
 from __future__ import annotations
 
@@ -106,6 +109,9 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="eager split target (0 = donation only)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=4000,
+                    help="training instances of the learned-vs-first-fail leg (0 = skip it)")
+    ap.add_argument("--learned-eval", type=int, default=1024)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 256 MiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
@@ -163,11 +169,11 @@ def main():
         assert r.count == 73712, f"13-queens count {r.count} != 73712"
     nodes = sum(r.nodes for r in rb_res) + sum(r.nodes for r in q_res)
     revs = sum(r.revisions for r in rb_res) + sum(r.revisions for r in q_res)
-    # the search kernel's launches in the timed region (RB slices and 13-queens
-    # run the same kernel variant)
-    launches = len(rb_res) + len(q_res)
-    bytes_per_launch = sum(r.alg_bytes for r in rb_res + q_res) / launches
-    ms_per_launch = sum(r.kernel_ms for r in rb_res + q_res) / launches
+    # the dominant kernel: the search kernel's RB-slice launches of the timed
+    # region (13-queens takes ~0.1% of the time, in its own autotuned variant)
+    launches = len(rb_res)
+    bytes_per_launch = sum(r.alg_bytes for r in rb_res) / launches
+    ms_per_launch = sum(r.kernel_ms for r in rb_res) / launches
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     traffic = traffic_per_launch(launches)
     out = {
@@ -192,13 +198,23 @@ def main():
         "revisions_per_s": revs / dt,
         "solutions": {"rb_slices": [r.count for r in rb_res], "queens13": q_res[0].count},
         "nodes": {"rb_slices": [r.nodes for r in rb_res], "queens13": q_res[0].nodes},
+        "kernel_ms": {"rb_slices": [round(r.kernel_ms, 3) for r in rb_res],
+                      "queens13": [round(r.kernel_ms, 3) for r in q_res]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "search_kernel (all launches of the timed steps)",
+                     "kernel": "search_kernel, RB-slice launches of the timed steps "
+                               f"(layout {tuned['rb']['chosen']})",
                      "launches": launches,
                      "kernel_ms_per_launch": ms_per_launch,
                      "alg_bytes_per_launch": bytes_per_launch},
     }
+    if args.learned_train > 0:
+        # time-to-all-solutions, learned vs first-fail (untimed leg, same GPU,
+        # same layout and launch for both policies)
+        from paper_1909_09213_amd import learn
+        rep = learn.experiment(ctx, n_train=args.learned_train, n_eval=args.learned_eval)
+        rep.pop("theta")
+        out["learned_vs_first_fail"] = rep
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out))

@@ -627,13 +627,16 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const bool use_var = feat == 0 && layout == CUBICS_LAYOUT_VAR && var_all;
     const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG, use_var);
     int wpb = use_var ? 8 : 4;
-    const size_t per_wave = (size_t)G.lds_words * 4;
+    // learned search: each worker also keeps its task's static features [n][4]
+    const int lds_words = G.lds_words + (feat == 1 ? 4 * G.nmax : 0);
+    const size_t per_wave = (size_t)lds_words * 4;
+    const size_t pol_bytes = feat == 1 ? (size_t)POLICY_LDS_WORDS * 4 : 0;  // network copy
     const size_t tab_bytes = (B == 1) ? (size_t)probs[0]->dev.blob_words * 4 : 0;
-    bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + per_wave <= LDS_WG_MAX;
-    size_t lds = (tl ? tab_bytes : 0) + per_wave * wpb;
+    bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + pol_bytes + per_wave <= LDS_WG_MAX;
+    size_t lds = (tl ? tab_bytes : 0) + pol_bytes + per_wave * wpb;
     while (wpb > 1 && lds > LDS_WG_MAX) {
         wpb /= 2;
-        lds = (tl ? tab_bytes : 0) + per_wave * wpb;
+        lds = (tl ? tab_bytes : 0) + pol_bytes + per_wave * wpb;
     }
     if (lds > LDS_WG_MAX) return fail(CUBICS_EUNSUPPORTED, "instance needs %zu bytes of LDS per worker", per_wave);
     int bpc = 0;
@@ -698,7 +701,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     P.split_target = L0.split_target;
     P.time_ticks = L0.time_ms > 0 ? (long long)L0.time_ms * ctx->wall_khz : 0;
     P.cancel = ctx->cancel_host;
-    P.lds_words = G.lds_words;
+    P.lds_words = lds_words;
     P.nmax = G.nmax;
     P.wmax = G.wmax;
     P.gmax = G.gmax;

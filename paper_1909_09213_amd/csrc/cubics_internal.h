@@ -100,6 +100,11 @@ constexpr int POLICY_H = 64;   // hidden units
 constexpr int POLICY_NP = POLICY_H * POLICY_F + POLICY_H + POLICY_H + 1;
 constexpr int OFF_W1 = 0, OFF_B1 = POLICY_H * POLICY_F, OFF_W2 = OFF_B1 + POLICY_H, OFF_B2 = OFF_W2 + POLICY_H;
 
+// LDS copy of the network for the learned search (words): w1 bf16 [64][16]
+// (512 words), b1 [64], w2 bf16 [64] (32 words), b2, padded to 16 bytes.
+constexpr int POLICY_LDS_W1 = 0, POLICY_LDS_B1 = 512, POLICY_LDS_W2 = 576, POLICY_LDS_B2 = 608;
+constexpr int POLICY_LDS_WORDS = 612;
+
 struct PolicyDev {
     const uint16_t *w1;  // [64][16] bf16, inputs >= POLICY_F zero
     const float *b1;     // [64] (inside theta)

@@ -186,25 +186,47 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 #pragma unroll
     for (int k = 0; k < WM; ++k) nw[k] = dt[k];
     if (ty == U_TABLE) {
-        uint32_t acc[WM];
+        if (pop_w(dt, W) < pop_w(ds, W)) {
+            // fewer target values: test each one's row (indexed by the target
+            // value, bits over the source) against D_src
+            const uint32_t *rows = I.rows + u.p0;
 #pragma unroll
-        for (int k = 0; k < WM; ++k) acc[k] = 0u;
-        const uint32_t *rows = I.rows + u.p1;
+            for (int w = 0; w < WM; ++w) {
+                if (w >= W) break;
+                uint32_t bits = dt[w];
+                while (bits) {
+                    const int a = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    const uint32_t *r = rows + (size_t)(32 * w + a) * W;
+                    uint32_t any = 0u;
 #pragma unroll
-        for (int w = 0; w < WM; ++w) {
-            if (w >= W) break;
-            uint32_t bits = ds[w];
-            while (bits) {
-                int b = 32 * w + __ffs(bits) - 1;
-                bits &= bits - 1;
-                const uint32_t *r = rows + (size_t)b * W;
-#pragma unroll
-                for (int k = 0; k < WM; ++k)
-                    if (k < W) acc[k] |= r[k];
+                    for (int k = 0; k < WM; ++k)
+                        if (k < W) any |= r[k] & ds[k];
+                    if (!any) nw[w] &= ~(1u << a);
+                }
             }
-        }
+        } else {
+            // union of the rows of the source values (bits over the target)
+            uint32_t acc[WM];
 #pragma unroll
-        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
+            for (int k = 0; k < WM; ++k) acc[k] = 0u;
+            const uint32_t *rows = I.rows + u.p1;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (w >= W) break;
+                uint32_t bits = ds[w];
+                while (bits) {
+                    int b = 32 * w + __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    const uint32_t *r = rows + (size_t)b * W;
+#pragma unroll
+                    for (int k = 0; k < WM; ++k)
+                        if (k < W) acc[k] |= r[k];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
+        }
     } else if (ty == U_NEQ) {
         if (pop_w(ds, W) == 1) {
             int a = low_w(ds, W) + u.p0;
@@ -288,6 +310,7 @@ struct Lds {
     u64 *gp;         // pending globals [ngw]
     uint32_t *fails; // [nmax] failures below each branching variable (policy feature)
     uint32_t *scr;   // 32 words scratch
+    float *feat;     // [nmax][4] learned search: the task's static features
 };
 
 // Process one chunk of binary units in LANE layout.  Returns wave-uniform fail.
@@ -891,11 +914,12 @@ constexpr int POLL = 128;  // nodes between checks of stop flags and donation re
 
 // Feature k (0..4) of variable i at a node of depth `depth`: domain fraction,
 // static degree / (n-1), mean static tightness, depth / n, log2(1 + fails).
-DEV float var_feature(const InstDev &I, int i, int k, int depth, int pop, uint32_t fails) {
+// fs: the instance's static features [n][4] (global or an LDS copy).
+DEV float var_feature(const InstDev &I, const float *fs, int i, int k, int depth, int pop, uint32_t fails) {
     switch (k) {
-    case 0: return (float)pop * I.feat_static[4 * i + 2];
-    case 1: return I.feat_static[4 * i + 0];
-    case 2: return I.feat_static[4 * i + 1];
+    case 0: return (float)pop * fs[4 * i + 2];
+    case 1: return fs[4 * i + 0];
+    case 2: return fs[4 * i + 1];
     case 3: return (float)depth / (float)(I.n > 0 ? I.n : 1);
     default: return log2f(1.f + (float)fails);
     }
@@ -928,14 +952,11 @@ DEV u64 mix64(u64 z) {  // SplitMix64 finalizer (Steele, Lea and Flood 2014)
 // Learned choice: the candidate (two or more values) with the smallest
 // predicted log-size of its subtree; lowest index on ties.  Candidates are
 // scored 16 at a time by the MFMA network.
+// pol: the network's LDS copy (staged once per workgroup).
 template <int WM>
-DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, int depth, int lane, int fallback) {
+DEV int choose_learned(const PolicyDev &pol, const InstDev &I, const Lds &L, int depth, int lane, int fallback) {
     const int n = I.n;
     const int row = lane & 15, kq = lane >> 4;
-    // opaque copies of the weight pointers: keeps the (loop-invariant) weight
-    // loads inside this call instead of hoisted, and live, across the search
-    PolicyDev pol = P.policy;
-    asm volatile("" : "+s"(pol.w1), "+s"(pol.b1), "+s"(pol.w2), "+s"(pol.b2));
     u64 best = ~0ull;
     for (int base = 0; base < n; base += 16) {
         const int i = base + row;
@@ -945,7 +966,7 @@ DEV int choose_learned(const SearchParams &P, const InstDev &I, const Lds &L, in
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int k = 4 * kq + j;
-            const float f = (i < n && k < POLICY_F) ? var_feature(I, i, k, depth, pop, L.fails[i]) : 0.f;
+            const float f = (i < n && k < POLICY_F) ? var_feature(I, L.feat, i, k, depth, pop, L.fails[i]) : 0.f;
             xT[j] = (short)f2bf(f);
         }
         const f32x4 acc = mlp_tile<true>(pol, xT, lane, nullptr);
@@ -1003,7 +1024,7 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
 template <int WM, int FEAT, bool GLOB, bool SEGC>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
-                  long long t_start) {
+                  long long t_start, const PolicyDev &LP) {
     const int n = I.n, W = I.W, nw = n * W;
     const int layout = P.layout;
     const uint32_t FW = P.frame_words;
@@ -1023,6 +1044,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     const bool learned = FEAT == 1 && P.branching == 1;
     if (tracing || learned) {
         for (int i = lane; i < n; i += 64) L.fails[i] = 0u;
+        if (learned)
+            for (int t = lane; t < 4 * n; t += 64) L.feat[t] = I.feat_static[t];
         wsync();
     }
 
@@ -1068,7 +1091,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 const u64 rnd = mix64(((u64)P.seed << 40) ^ ((u64)(blockIdx.x * 16 + (threadIdx.x >> 6)) << 24) ^ C.stamp);
                 if ((int)(rnd % 1000ull) < P.explore_pm) x = choose_explore<WM>(I, L, lane, rnd >> 20);
             } else if (learned) {
-                x = choose_learned<WM>(P, I, L, depth, lane, open_x);
+                x = choose_learned<WM>(LP, I, L, depth, lane, open_x);
             }
             // eager split: hand every child to the queue while the split target is unmet
             bool split = false;
@@ -1135,7 +1158,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 frame_store_meta<WM>(f, F, lane);
                 if (tracing) {
                     const int px = var_pop<WM>(I, L, x);
-                    if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, x, lane, depth, px, L.fails[x]);
+                    if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, I.feat_static, x, lane, depth, px, L.fails[x]);
                     if (lane == 0) {
                         f[24] = (uint32_t)C.stamp;
                         f[25] = (uint32_t)(C.stamp >> 32);
@@ -1689,8 +1712,31 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         __syncthreads();
         IL = rebase(G, lds_raw);
     }
+    // learned search: the network's weights staged once per workgroup in LDS
+    // (every branching reads all of them)
+    PolicyDev LP = P.policy;
+    uint32_t pol_words = 0;
+    if (FEAT == 1) {
+        uint32_t *pw = lds_raw + tab_words;
+        const uint32_t *w1g = (const uint32_t *)P.policy.w1;
+        const uint32_t *w2g = (const uint32_t *)P.policy.w2;
+        for (int t = threadIdx.x; t < POLICY_LDS_WORDS; t += blockDim.x) {
+            uint32_t v = 0u;
+            if (t < POLICY_LDS_B1) v = w1g[t];
+            else if (t < POLICY_LDS_W2) v = __float_as_uint(P.policy.b1[t - POLICY_LDS_B1]);
+            else if (t < POLICY_LDS_B2) v = w2g[t - POLICY_LDS_W2];
+            else if (t == POLICY_LDS_B2) v = __float_as_uint(*P.policy.b2);
+            pw[t] = v;
+        }
+        __syncthreads();
+        LP.w1 = (const uint16_t *)(pw + POLICY_LDS_W1);
+        LP.b1 = (const float *)(pw + POLICY_LDS_B1);
+        LP.w2 = (const uint16_t *)(pw + POLICY_LDS_W2);
+        LP.b2 = (const float *)(pw + POLICY_LDS_B2);
+        pol_words = POLICY_LDS_WORDS;
+    }
     if (wid >= P.nworkers) return;
-    uint32_t *base = lds_raw + tab_words + (size_t)wave * P.lds_words;
+    uint32_t *base = lds_raw + tab_words + pol_words + (size_t)wave * P.lds_words;
     Lds L;
     const int ndw = (P.nmax + 63) >> 6, ngw = (P.gmax + 63) >> 6;
     int off = 0;
@@ -1705,6 +1751,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     L.fails = base + off;
     off += (P.nmax + 1) & ~1;
     L.scr = base + off;
+    L.feat = FEAT == 1 ? (float *)(base + off + 32) : nullptr;
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
     const long long t_start = (long long)wall_clock64();
     Counters C = {};
@@ -1762,7 +1809,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
             if (VAR)
                 run_task_var<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
             else
-                run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
+                run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start, LP);
         }
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
@@ -1780,7 +1827,7 @@ __global__ void features_kernel(const InstDev *inst, const uint32_t *dom, int de
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < I.n; i += gridDim.x * blockDim.x) {
         int pop = 0;
         for (int k = 0; k < I.W; ++k) pop += __popc(dom[i * I.W + k]);
-        for (int k = 0; k < POLICY_F; ++k) out[i * POLICY_F + k] = var_feature(I, i, k, depth, pop, 0u);
+        for (int k = 0; k < POLICY_F; ++k) out[i * POLICY_F + k] = var_feature(I, I.feat_static, i, k, depth, pop, 0u);
     }
 }
 
@@ -1842,6 +1889,7 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
     L.fails = lds_raw + off;
     off += (P.nmax + 1) & ~1;
     L.scr = lds_raw + off;
+    L.feat = nullptr;
     const int n = I.n, W = I.W, nw = n * W;
     for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
     wsync();

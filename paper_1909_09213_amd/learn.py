@@ -92,9 +92,10 @@ def sample_nodes(ctx: cb.Context, insts, seed: int = 0):
     """One search node per instance: a random descent from the root (the
     branching variable by first-fail on half of the steps, else uniform among
     the unassigned; the value uniform), propagated on the GPU after every
-    branching, to a depth drawn uniformly in [1, n/2]; a descent that fails
-    stops at its last consistent node.  Returns (index, depth, domains) with
-    the fixpoint domains of the node ([n, W] words)."""
+    branching, to a depth drawn uniformly in [1, n/2]; a branching whose
+    propagation fails is redrawn (up to 4 times), then the descent stops at
+    its last consistent node.  Returns (index, depth, domains) with the
+    fixpoint domains of the node ([n, W] words)."""
     rng = np.random.default_rng(seed)
     out = []
     for k, inst in enumerate(insts):
@@ -110,19 +111,25 @@ def sample_nodes(ctx: cb.Context, insts, seed: int = 0):
             free = np.flatnonzero(pops >= 2)
             if free.size == 0:
                 break
-            if rng.integers(0, 2) == 0:
-                x = int(free[np.lexsort((free, pops[free]))[0]])
-            else:
-                x = int(rng.choice(free))
-            vals = [32 * w + b for w in range(dom.shape[1]) for b in range(32) if (int(dom[x, w]) >> b) & 1]
-            a = int(rng.choice(vals))
-            init = dom.copy()
-            init[x] = 0
-            init[x, a // 32] = np.uint32(1 << (a % 32))
-            prob = ctx.load(inst.with_init(init))
-            failed, child = ctx.root(prob, device_words=True)
-            prob.free()
-            if failed:
+            child = None
+            for _ in range(4):
+                if rng.integers(0, 2) == 0:
+                    x = int(free[np.lexsort((free, pops[free]))[0]])
+                else:
+                    x = int(rng.choice(free))
+                vals = [32 * w + b for w in range(dom.shape[1]) for b in range(32)
+                        if (int(dom[x, w]) >> b) & 1]
+                a = int(rng.choice(vals))
+                init = dom.copy()
+                init[x] = 0
+                init[x, a // 32] = np.uint32(1 << (a % 32))
+                prob = ctx.load(inst.with_init(init[:, :inst.W]))
+                failed, c = ctx.root(prob, device_words=True)
+                prob.free()
+                if not failed:
+                    child = c
+                    break
+            if child is None:
                 break
             dom, depth = child, depth + 1
         if depth >= 1:
@@ -228,7 +235,12 @@ def train(ctx: cb.Context, rec, steps: int = 300, lr: float = 3e-3, seed: int = 
 def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_nodes: int = 0):
     """Solve every instance under first-fail and under the policy (one batched
     launch each, both in the LANE layout, which the learned path uses).
-    Returns per-policy totals and per-instance results."""
+    Returns per-policy totals and per-instance results.  With a node budget,
+    the instances first-fail resolves within it are solved again (budget x8)
+    in one launch per policy: "resolved_kernel_ms" is the
+    time-to-all-solutions of that set (the budget-capped launches are
+    dominated by instances that stop at the budget, where both policies do
+    the same number of nodes)."""
     probs = [ctx.load(x) for x in insts]
     out = {}
     for name, br, pol in (("first_fail", cb.BRANCH_FIRST_FAIL, None),
@@ -239,6 +251,30 @@ def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_node
         dt = time.perf_counter() - t0
         out[name] = {"results": res, "nodes": sum(r.nodes for r in res),
                      "kernel_ms": res[0].kernel_ms, "wall_s": dt}
+    if max_nodes:
+        keep = [i for i, r in enumerate(out["first_fail"]["results"]) if r.verdict != "LIMIT"]
+        sub = [probs[i] for i in keep]
+        out["resolved_by_first_fail"] = keep
+        for name, br, pol in (("first_fail", cb.BRANCH_FIRST_FAIL, None),
+                              ("learned", cb.BRANCH_LEARNED, policy)):
+            res = ctx.solve_batch(sub, mode, branching=br, policy=pol, layout=cb.LAYOUT_LANE,
+                                  max_nodes=8 * max_nodes) if sub else []
+            out[name]["resolved_kernel_ms"] = res[0].kernel_ms if res else 0.0
+            out[name]["resolved_nodes"] = sum(r.nodes for r in res)
+            out[name]["resolved_over_8x_budget"] = sum(r.verdict == "LIMIT" for r in res)
+        # time-to-all of single instances: the first `single` resolved ones,
+        # each in its own launch under both policies
+        single = keep[:128]
+        ratios = []
+        for i in single:
+            t = []
+            for br, pol in ((cb.BRANCH_FIRST_FAIL, None), (cb.BRANCH_LEARNED, policy)):
+                r = ctx.solve(probs[i], mode, branching=br, policy=pol, layout=cb.LAYOUT_LANE,
+                              max_nodes=8 * max_nodes)
+                t.append(r.kernel_ms)
+            ratios.append(t[1] / max(t[0], 1e-6))
+        out["single_instances"] = len(single)
+        out["single_time_ratio_geomean"] = float(np.exp(np.mean(np.log(ratios)))) if ratios else None
     for p in probs:
         p.free()
     return out
@@ -283,9 +319,19 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
         "node_ratio_geomean": float(np.exp(np.mean(np.log(ratios)))) if len(both) else None,
         "instances_fewer_nodes": int((ratios < 1).sum()),
         "instances_more_nodes": int((ratios > 1).sum()),
-        "time_to_all_ms_first_fail": ev["first_fail"]["kernel_ms"],
-        "time_to_all_ms_learned": ev["learned"]["kernel_ms"],
-        "time_ratio_learned_over_ff": ev["learned"]["kernel_ms"] / max(ev["first_fail"]["kernel_ms"], 1e-9),
+        "budget_per_instance": eval_max_nodes,
+        "capped_launch_ms_first_fail": ev["first_fail"]["kernel_ms"],
+        "capped_launch_ms_learned": ev["learned"]["kernel_ms"],
+        "resolved_by_first_fail": len(ev["resolved_by_first_fail"]),
+        "time_to_all_ms_first_fail": ev["first_fail"]["resolved_kernel_ms"],
+        "time_to_all_ms_learned": ev["learned"]["resolved_kernel_ms"],
+        "time_ratio_learned_over_ff": ev["learned"]["resolved_kernel_ms"]
+        / max(ev["first_fail"]["resolved_kernel_ms"], 1e-9),
+        "resolved_nodes_first_fail": ev["first_fail"]["resolved_nodes"],
+        "resolved_nodes_learned": ev["learned"]["resolved_nodes"],
+        "resolved_over_8x_budget_learned": ev["learned"]["resolved_over_8x_budget"],
+        "single_instance_launches": ev["single_instances"],
+        "single_instance_time_ratio_geomean": ev["single_time_ratio_geomean"],
         "seconds": {"generate": t_gen, "label": t_collect, "train": t_train},
         "theta": pol.get().tolist(),
     }

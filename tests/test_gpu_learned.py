@@ -161,6 +161,33 @@ def test_features_match_their_definition(ctx, cb):
     assert np.allclose(got, want, rtol=1e-6, atol=1e-7), np.max(np.abs(got - want))
     # NULL domains = the initial ones
     got0 = ctx.features(p, None, depth=0)
-    pop0 = np.array([sum(bin(int(w)).count("1") for w in row) for row in sub.full_init()])
+    pop0 = np.array([sum(bin(int(w)).count("1") for w in row) for row in sub.init])
+    assert pop0[0] == 1 and pop0[3] == 1 and pop0[1] == inst.dsize[1]
     assert np.allclose(got0[:, 0], pop0 / inst.dsize, rtol=1e-6)
     assert np.all(got0[:, 3] == 0)
+
+
+def test_trained_policy_gains_over_first_fail(ctx, cb):
+    """Train on sibling subtree sizes at nodes of 600 seeded instances, then
+    count 256 held-out instances under first-fail and under the policy (same
+    layout, same launch): identical counts, and fewer nodes on most
+    instances (the geometric mean of the per-instance node ratios)."""
+    from paper_1909_09213_amd import learn
+    train = learn.instances(cspgen.SEED_TRAIN, 600)
+    nodes = learn.sample_nodes(ctx, train, seed=1)
+    rec = learn.sibling_records(ctx, train, nodes, seed=1)
+    pol, losses = learn.train(ctx, rec, steps=800, lr=1e-2)
+    held = learn.instances(cspgen.SEED_EVAL, 256)
+    ev = learn.evaluate(ctx, held, pol, cb.MODE_COUNT, max_nodes=20_000_000)
+    ff, le = ev["first_fail"]["results"], ev["learned"]["results"]
+    both = [i for i in range(len(held)) if ff[i].verdict != "LIMIT" and le[i].verdict != "LIMIT"]
+    assert len(both) >= 200
+    for i in both:
+        assert (ff[i].count, ff[i].verdict) == (le[i].count, le[i].verdict), held[i].name
+    r = np.array([le[i].nodes / ff[i].nodes for i in both])
+    geo = float(np.exp(np.mean(np.log(r))))
+    print(f"records {rec.shape[0]}, loss {losses[0]:.3f} -> {losses[-1]:.3f}; node ratio geomean "
+          f"{geo:.3f}, fewer {int((r < 1).sum())}, more {int((r > 1).sum())}; kernel ms "
+          f"{ev['first_fail']['kernel_ms']:.0f} -> {ev['learned']['kernel_ms']:.0f}", file=sys.stderr)
+    assert geo < 0.9
+    assert (r < 1).sum() > 2 * (r > 1).sum()
