@@ -186,47 +186,26 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 #pragma unroll
     for (int k = 0; k < WM; ++k) nw[k] = dt[k];
     if (ty == U_TABLE) {
-        if (pop_w(dt, W) < pop_w(ds, W)) {
-            // fewer target values: test each one's row (indexed by the target
-            // value, bits over the source) against D_src
-            const uint32_t *rows = I.rows + u.p0;
+        // union of the rows of the source values (bits over the target)
+        uint32_t acc[WM];
 #pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (w >= W) break;
-                uint32_t bits = dt[w];
-                while (bits) {
-                    const int a = __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    const uint32_t *r = rows + (size_t)(32 * w + a) * W;
-                    uint32_t any = 0u;
+        for (int k = 0; k < WM; ++k) acc[k] = 0u;
+        const uint32_t *rows = I.rows + u.p1;
 #pragma unroll
-                    for (int k = 0; k < WM; ++k)
-                        if (k < W) any |= r[k] & ds[k];
-                    if (!any) nw[w] &= ~(1u << a);
-                }
+        for (int w = 0; w < WM; ++w) {
+            if (w >= W) break;
+            uint32_t bits = ds[w];
+            while (bits) {
+                int b = 32 * w + __ffs(bits) - 1;
+                bits &= bits - 1;
+                const uint32_t *r = rows + (size_t)b * W;
+#pragma unroll
+                for (int k = 0; k < WM; ++k)
+                    if (k < W) acc[k] |= r[k];
             }
-        } else {
-            // union of the rows of the source values (bits over the target)
-            uint32_t acc[WM];
-#pragma unroll
-            for (int k = 0; k < WM; ++k) acc[k] = 0u;
-            const uint32_t *rows = I.rows + u.p1;
-#pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (w >= W) break;
-                uint32_t bits = ds[w];
-                while (bits) {
-                    int b = 32 * w + __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    const uint32_t *r = rows + (size_t)b * W;
-#pragma unroll
-                    for (int k = 0; k < WM; ++k)
-                        if (k < W) acc[k] |= r[k];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
         }
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
     } else if (ty == U_NEQ) {
         if (pop_w(ds, W) == 1) {
             int a = low_w(ds, W) + u.p0;
@@ -572,9 +551,11 @@ DEV bool revise_linear(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt,
         for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
         const long long at = co[1 + t];
         const long long mn = (long long)I.lo[v] + low_w(d, W);
-        const long long rest = S - at * mn;
-        const long long ubv = floor_div(b - rest, at);
-        const long long ubi = ubv - I.lo[v];
+        const long long slack = b - (S - at * mn);  // >= at * mn, since S <= b
+        const long long mx = (long long)I.lo[v] + high_w(d, W);
+        // only a variable whose largest value breaks the bound needs the
+        // (64-bit) division for its new upper bound
+        const long long ubi = at * mx > slack ? floor_div(slack, at) - I.lo[v] : 32LL * W;
         if (ubi < 32LL * W - 1) {
             const int ub = (int)ubi;  // >= the min index, since S <= b
             bool ch = false;
