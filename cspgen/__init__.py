@@ -27,8 +27,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-UNARY, TABLE2, NEQ, LT, QUEENS, ALLDIFF, LINEAR_LE = range(7)
-TYPE_NAMES = ["UNARY", "TABLE2", "NEQ", "LT", "QUEENS", "ALLDIFF", "LINEAR_LE"]
+UNARY, TABLE2, NEQ, LT, QUEENS, ALLDIFF, LINEAR_LE, ALLDIFF_GAC = range(8)
+TYPE_NAMES = ["UNARY", "TABLE2", "NEQ", "LT", "QUEENS", "ALLDIFF", "LINEAR_LE", "ALLDIFF_GAC"]
 
 GOLDEN64 = 0x9E3779B97F4A7C15
 
@@ -152,6 +152,14 @@ class Instance:
         if init is not None:
             init = np.ascontiguousarray(init, dtype=np.uint32).reshape(self.n, self.W)
             out.init = init.copy()
+        return out
+
+    def with_gac(self) -> "Instance":
+        """Copy whose all-different constraints are of the generalized-arc-
+        consistency kind (same constraints, same solutions)."""
+        out = self.with_init(self.init)
+        out.type = np.where(self.type == ALLDIFF, ALLDIFF_GAC, self.type).astype(self.type.dtype)
+        out.name = self.name + "_gac"
         return out
 
     def full_init(self) -> np.ndarray:

@@ -22,7 +22,9 @@
  *    constraint (table, !=, <, queens pair as one constraint), singleton
  *    elimination plus a pigeonhole test for all-different, and bounds
  *    reasoning for sum a_t x_t <= b with positive a_t; unary constraints
- *    restrict the root domains;
+ *    restrict the root domains; the all-different of type 7 is propagated
+ *    to generalized arc consistency instead (the stronger propagation the
+ *    paper names as future work, Sec. 3);
  *  - a node is every propagation call: the root and every child tried,
  *    failed children included;
  *  - a table constraint is given over the original domains and is
@@ -38,7 +40,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { T_UNARY = 0, T_TABLE2 = 1, T_NEQ = 2, T_LT = 3, T_QUEENS = 4, T_ALLDIFF = 5, T_LINEAR = 6 };
+enum { T_UNARY = 0, T_TABLE2 = 1, T_NEQ = 2, T_LT = 3, T_QUEENS = 4, T_ALLDIFF = 5, T_LINEAR = 6,
+       T_ALLDIFF_GAC = 7 };
 enum { M_FIRST = 0, M_ALL = 1, M_COUNT = 2 };
 enum { V_SAT = 0, V_UNSAT = 1, V_LIMIT = 2 };
 
@@ -213,6 +216,83 @@ static int revise_alldiff(ctx_t *C, unsigned char *D, int c, unsigned char *chg)
     return status;
 }
 
+/* Kuhn's augmenting path from scope variable u (index into the scope) over
+   the value indices of its domain; mv[v] = scope index matched to value v. */
+static int kuhn_try(const unsigned char *adj, int span, int u, int *mv, unsigned char *seen) {
+    for (int v = 0; v < span; ++v) {
+        if (!adj[(int64_t)u * span + v] || seen[v]) continue;
+        seen[v] = 1;
+        if (mv[v] < 0 || kuhn_try(adj, span, mv[v], mv, seen)) {
+            mv[v] = u;
+            return 1;
+        }
+    }
+    return 0;
+}
+
+/* Does the scope have an assignment of pairwise different values from adj
+   (scope index x value index)?  A maximum bipartite matching covers the scope. */
+static int has_sdr(const unsigned char *adj, int k, int span, int *mv, unsigned char *seen) {
+    for (int v = 0; v < span; ++v) mv[v] = -1;
+    for (int u = 0; u < k; ++u) {
+        memset(seen, 0, (size_t)span);
+        if (!kuhn_try(adj, span, u, mv, seen)) return 0;
+    }
+    return 1;
+}
+
+/* All-different to generalized arc consistency, from the definition: value v
+   stays in D_x iff the scope can take pairwise different values from its
+   domains with x = v (one matching test per variable-value pair). */
+static int revise_alldiff_gac(ctx_t *C, unsigned char *D, int c, unsigned char *chg) {
+    const orc_problem *P = C->P;
+    int k = P->arity[c];
+    const int32_t *sc = P->vars + P->var_off[c];
+    int64_t vmin = INT64_MAX, vmax = INT64_MIN;
+    for (int u = 0; u < k; ++u) {
+        int x = sc[u];
+        if (P->lo[x] < vmin) vmin = P->lo[x];
+        if ((int64_t)P->lo[x] + P->dsize[x] - 1 > vmax) vmax = (int64_t)P->lo[x] + P->dsize[x] - 1;
+    }
+    int span = (int)(vmax - vmin + 1);
+    unsigned char *adj = (unsigned char *)calloc((size_t)k * span, 1);
+    unsigned char *keep = (unsigned char *)calloc((size_t)k * span, 1);
+    unsigned char *seen = (unsigned char *)malloc((size_t)span);
+    int *mv = (int *)malloc(sizeof(int) * (size_t)span);
+    for (int u = 0; u < k; ++u) {
+        int x = sc[u];
+        for (int a = 0; a < P->dsize[x]; ++a)
+            if (D[(int64_t)x * C->dmax + a]) adj[(int64_t)u * span + (value_of(C, x, a) - vmin)] = 1;
+    }
+    for (int u = 0; u < k; ++u) {
+        unsigned char *row = (unsigned char *)malloc((size_t)span);
+        memcpy(row, adj + (int64_t)u * span, (size_t)span);
+        for (int v = 0; v < span; ++v) {
+            if (!row[v]) continue;
+            memset(adj + (int64_t)u * span, 0, (size_t)span);
+            adj[(int64_t)u * span + v] = 1;
+            keep[(int64_t)u * span + v] = (unsigned char)has_sdr(adj, k, span, mv, seen);
+        }
+        memcpy(adj + (int64_t)u * span, row, (size_t)span);
+        free(row);
+    }
+    int status = 0;
+    for (int u = 0; u < k; ++u) {
+        int x = sc[u];
+        for (int a = 0; a < P->dsize[x]; ++a) {
+            unsigned char *cell = D + (int64_t)x * C->dmax + a;
+            if (*cell && !keep[(int64_t)u * span + (value_of(C, x, a) - vmin)]) {
+                *cell = 0;
+                chg[x] = 1;
+                status |= 1;
+            }
+        }
+        if (dom_size(C, D, x) == 0) status |= 2;
+    }
+    free(adj); free(keep); free(seen); free(mv);
+    return status;
+}
+
 /* sum_t a_t x_t <= b with every a_t > 0: with S the sum of a_t * min(D_t),
    fail if S > b; otherwise remove every value v of D_t with
    a_t * v + (S - a_t * min(D_t)) > b. */
@@ -266,9 +346,11 @@ static int propagate(ctx_t *C, unsigned char *D, unsigned char *chg) {
         C->st.revisions++;
         int c = C->prop[p].con, ty = C->P->type[c];
         int status;
-        if (ty == T_ALLDIFF || ty == T_LINEAR) {
+        if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC) {
             memset(chg, 0, (size_t)C->n);
-            status = ty == T_ALLDIFF ? revise_alldiff(C, D, c, chg) : revise_linear(C, D, c, chg);
+            status = ty == T_ALLDIFF   ? revise_alldiff(C, D, c, chg)
+                     : ty == T_LINEAR ? revise_linear(C, D, c, chg)
+                                      : revise_alldiff_gac(C, D, c, chg);
             if (status & 2) goto fail;
             for (int v = 0; v < C->n; ++v)
                 if (chg[v]) enqueue_var(C, v);
@@ -361,8 +443,12 @@ static int setup(ctx_t *C, const orc_problem *P) {
             if (k != 2 || sc[0] == sc[1]) return -1;
             C->prop[C->nprop].con = c; C->prop[C->nprop].dir = 0; C->nprop++;
             C->prop[C->nprop].con = c; C->prop[C->nprop].dir = 1; C->nprop++;
-        } else if (ty == T_ALLDIFF || ty == T_LINEAR) {
+        } else if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC) {
             if (k < 1) return -1;
+            if (ty == T_ALLDIFF_GAC)  /* a scope is a set of variables */
+                for (int t = 0; t < k; ++t)
+                    for (int u = t + 1; u < k; ++u)
+                        if (sc[t] == sc[u]) return -1;
             if (ty == T_LINEAR)
                 for (int t = 0; t < k; ++t)
                     if (P->params[P->par_off[c] + 1 + t] <= 0) return -1;
@@ -516,6 +602,7 @@ int orc_verify(const orc_problem *P, const int32_t *x) {
             break;
         }
         case T_ALLDIFF:
+        case T_ALLDIFF_GAC:
             for (int u = 0; u < k; ++u)
                 for (int w = u + 1; w < k; ++w)
                     if (x[sc[u]] == x[sc[w]]) return 0;

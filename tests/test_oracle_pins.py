@@ -398,6 +398,20 @@ def _def_fixpoint(inst, D):
                     return None
                 if len(set().union(*[D[u] for u in sc])) < len(sc):
                     return None
+            elif ty == 7:
+                # generalized arc consistency: a value stays iff it occurs in
+                # some tuple of pairwise different values (enumerated)
+                keep = [set() for _ in sc]
+                for tup in itertools.product(*[sorted(D[u]) for u in sc]):
+                    if len(set(tup)) == len(tup):
+                        for q, v in enumerate(tup):
+                            keep[q].add(v)
+                for q, u in enumerate(sc):
+                    if keep[q] != D[u]:
+                        D[u] = keep[q]
+                        changed = True
+                if any(not D[u] for u in sc):
+                    return None
             elif ty == 6:
                 par = [int(v) for v in inst.par(c)]
                 b, coef = par[0], par[1:]
@@ -529,3 +543,75 @@ def test_rb_slices_partition_the_tree():
     assert sum(p.count for p in parts) == full.count
     assert sum(p.nodes for p in parts) == full.nodes - 1
     assert sum(p.fails for p in parts) == full.fails
+
+
+# ------------------------------------------------- all-different, GAC kind
+
+def test_gac_alldiff_root_is_projection():
+    """One all-different of the generalized-arc-consistency kind over random
+    initial domains: the root fixpoint keeps exactly the values that occur in
+    some assignment of pairwise different values (enumerated)."""
+    rng = np.random.default_rng(7)
+    seen_prune = 0
+    for trial in range(150):
+        k = int(rng.integers(2, 6))
+        d = int(rng.integers(k - 1, 7))
+        lo = [int(v) for v in rng.integers(-2, 3, k)]
+        inst = _custom(k, lo, [d] * k, [(7, tuple(range(k)), (), ())])
+        init = np.zeros((k, 1), np.uint32)
+        for i in range(k):
+            bits = rng.integers(0, 2, d)
+            if bits.sum() == 0:
+                bits[rng.integers(0, d)] = 1
+            init[i, 0] = int(sum(int(b) << a for a, b in enumerate(bits)))
+        sub = inst.with_init(init)
+        doms = [[lo[i] + a for a in range(d) if (int(init[i, 0]) >> a) & 1] for i in range(k)]
+        proj = [set() for _ in range(k)]
+        for tup in itertools.product(*doms):
+            if len(set(tup)) == k:
+                for q, v in enumerate(tup):
+                    proj[q].add(v)
+        failed, bits, _ = oracle.root(sub)
+        if not proj[0]:
+            assert failed
+            continue
+        assert not failed
+        got = _bits_to_values(sub, bits)
+        assert got == [sorted(p) for p in proj], trial
+        seen_prune += any(len(proj[q]) < len(doms[q]) for q in range(k))
+    assert seen_prune > 20
+
+
+def test_gac_alldiff_prunes_what_singletons_miss():
+    # x0, x1 in {1, 2}, x2 in {1, 2, 3}: the pair x0, x1 takes both 1 and 2,
+    # so GAC leaves x2 = 3 at the root; singleton elimination keeps all three
+    inst = _custom(3, [1, 1, 1], [3, 3, 3], [(7, (0, 1, 2), (), ())])
+    sub = inst.with_init(np.array([[0b011], [0b011], [0b111]], np.uint32))
+    failed, bits, _ = oracle.root(sub)
+    assert not failed and _bits_to_values(sub, bits) == [[1, 2], [1, 2], [3]]
+    weak = sub.with_init(sub.init)
+    weak.type = np.array([5], np.int32)
+    failed, bits, _ = oracle.root(weak)
+    assert not failed and _bits_to_values(weak, bits) == [[1, 2], [1, 2], [1, 2, 3]]
+
+
+def test_gac_alldiff_counts_and_nodes():
+    """Same solutions as the singleton/pigeonhole all-different, never more
+    nodes; node counts equal an independent search over the enumerated GAC."""
+    fewer = 0
+    for idx in range(40):
+        inst = cspgen.mixed(idx + 900, n=5, dmax=5, m=5, type_mask=(1 << 5) | (1 << 1) | (1 << 2))
+        gac = inst.with_gac()
+        a = oracle.solve(inst, oracle.MODE_COUNT)
+        b = oracle.solve(gac, oracle.MODE_COUNT)
+        assert a.count == b.count and b.nodes <= a.nodes, idx
+        fewer += b.nodes < a.nodes
+        s = _def_search(gac)
+        assert (b.count, b.nodes, b.fails) == (s["count"], s["nodes"], s["fails"]), idx
+    for k, s_ in ((3, 3), (4, 6), (5, 5)):
+        inst = _custom(k, [0] * k, [s_] * k, [(7, tuple(range(k)), (), ())])
+        r = oracle.solve(inst, oracle.MODE_COUNT)
+        assert r.count == math.factorial(s_) // math.factorial(s_ - k) and r.fails == 0
+    g = cspgen.global_twin(1)
+    assert oracle.solve(g.with_gac(), oracle.MODE_COUNT).count == oracle.solve(g, oracle.MODE_COUNT).count
+    assert fewer > 0
