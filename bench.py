@@ -142,7 +142,8 @@ def main():
 
     # the library's autotuner picks the revision layout for each shape (untimed)
     tuned = {}
-    for name, p, t in (("rb", slices[15], 400), ("queens13", q13, 100)):
+    # windows long enough that start-up and drain do not decide the choice
+    for name, p, t in (("rb", slices[15], 1500), ("queens13", q13, 100)):
         chosen, div, rates = ctx.autotune([p], cb.MODE_COUNT, time_ms=t, rates=True)
         names = {1: "lane", 2: "seg", 3: "var"}
         tuned[name] = {"chosen": names[chosen], "worker_divisor": div,

@@ -49,7 +49,15 @@ extern "C" {
  *   NEQ        scope (i,j)  params {off}: x_i != x_j + off
  *   LT         scope (i,j)  params {off}: x_i <  x_j + off
  *   QUEENS     scope (i,j)  params {k}:   x_i != x_j and |x_i - x_j| != k
- *   ALLDIFF    scope (v_0..v_{k-1}), all with the same lo: pairwise distinct
+ *   ALLDIFF    scope (v_0..v_{k-1}): pairwise distinct values (domains are
+ *              compared in value space; the scope's value span must fit
+ *              CUBICS_MAX_DOMAIN); propagated by singleton elimination and a
+ *              pigeonhole test
+ *   ALLDIFF_GAC  the same constraint, propagated to generalized arc
+ *              consistency (a value stays iff some assignment of pairwise
+ *              different values uses it: maximum matching and strongly
+ *              connected components, the stronger propagation of Sec. 3);
+ *              at most 64 variables, else CUBICS_EUNSUPPORTED
  *   LINEAR_LE  scope (v_0..v_{k-1}); params {b, a_0..a_{k-1}}, every a_t > 0:
  *                           sum_t a_t x_{v_t} <= b
  */
@@ -60,7 +68,8 @@ enum {
     CUBICS_LT = 3,
     CUBICS_QUEENS = 4,
     CUBICS_ALLDIFF = 5,
-    CUBICS_LINEAR_LE = 6
+    CUBICS_LINEAR_LE = 6,
+    CUBICS_ALLDIFF_GAC = 7
 };
 
 /* solve modes */

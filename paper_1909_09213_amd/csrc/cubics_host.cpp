@@ -103,6 +103,7 @@ struct cubics_prob {
     int n = 0, W = 1, dmax = 1;
     int n_units = 0, n_glob = 0;
     bool has_table = false;
+    bool has_gac = false;  // a GAC all-different (needs the larger LDS scratch)
     std::string bucket;
 };
 
@@ -208,7 +209,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     // ALLDIFF scopes compare domains in value space: widen W to their spans
     int span_words = 1;
     for (int c = 0; c < m; ++c) {
-        if (type[c] != CUBICS_ALLDIFF) continue;
+        if (type[c] != CUBICS_ALLDIFF && type[c] != CUBICS_ALLDIFF_GAC) continue;
         const int k = arity[c];
         if (k < 1 || var_off[c + 1] - var_off[c] != k) continue;  // reported below
         const int32_t *sc = vars + var_off[c];
@@ -246,7 +247,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     std::vector<int32_t> unary;
     std::vector<int32_t> deg(std::max(n, 1), 0);
     std::vector<double> tight_sum(std::max(n, 1), 0.0);
-    bool has_table = false;
+    bool has_table = false, has_gac = false;
     for (int c = 0; c < m; ++c) {
         const int ty = type[c], k = arity[c];
         if (var_off[c + 1] - var_off[c] != k || k < 1)
@@ -317,13 +318,19 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                     tight_sum[i] += 3.0 / dj; tight_sum[j] += 3.0 / di;
                 }
             }
-        } else if (ty == CUBICS_ALLDIFF || ty == CUBICS_LINEAR_LE) {
+        } else if (ty == CUBICS_ALLDIFF || ty == CUBICS_ALLDIFF_GAC || ty == CUBICS_LINEAR_LE) {
             GDesc g;
-            g.type = ty == CUBICS_ALLDIFF ? G_ALLDIFF : G_LINEAR;
+            g.type = ty == CUBICS_ALLDIFF ? G_ALLDIFF : ty == CUBICS_ALLDIFF_GAC ? G_ALLDIFF_GAC : G_LINEAR;
+            if (ty == CUBICS_ALLDIFF_GAC) {
+                if (k > GAC_MAX_K)
+                    return fail(CUBICS_EUNSUPPORTED, "constraint %d: ALLDIFF_GAC over %d > %d variables", c, k,
+                                GAC_MAX_K);
+                has_gac = true;
+            }
             g.k = k;
             g.scope_off = (int32_t)gscope.size();
             g.coef_off = (int32_t)gcoef.size();
-            if (ty == CUBICS_ALLDIFF) {
+            if (ty != CUBICS_LINEAR_LE) {
                 // the scope's domains are compared in value space: base = the
                 // smallest lo; the span must fit the instance's domain words
                 int base = lo[sc[0]], top = lo[sc[0]] + dsize[sc[0]];
@@ -332,7 +339,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                     top = std::max(top, (int)(lo[sc[t]] + dsize[sc[t]]));
                 }
                 if (top - base > CUBICS_MAX_DOMAIN)
-                    return fail(CUBICS_EUNSUPPORTED, "constraint %d: ALLDIFF value span %d exceeds %d", c,
+                    return fail(CUBICS_EUNSUPPORTED, "constraint %d: all-different value span %d exceeds %d", c,
                                 top - base, CUBICS_MAX_DOMAIN);
                 g.coef_off = base;
                 for (int t = 0; t < k; ++t) tight_sum[sc[t]] += (double)(k - 1) / dsize[sc[t]];
@@ -462,6 +469,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     p->n_units = (int)sorted.size();
     p->n_glob = (int)gdesc.size();
     p->has_table = has_table;
+    p->has_gac = has_gac;
     char *b8 = (char *)blob;
     InstDev &I = p->dev;
     memset(&I, 0, sizeof I);
@@ -537,6 +545,7 @@ int pow2_ge(int x) {
 struct Geometry {
     int nmax = 1, wmax = 1, gmax = 0;
     int lds_words = 0;
+    bool gac = false;
 };
 
 Geometry geometry(cubics_prob *const *probs, int B) {
@@ -546,11 +555,12 @@ Geometry geometry(cubics_prob *const *probs, int B) {
         g.nmax = std::max(g.nmax, probs[b]->n);
         wm = std::max(wm, probs[b]->W);
         g.gmax = std::max(g.gmax, probs[b]->n_glob);
+        g.gac |= probs[b]->has_gac;
     }
     g.wmax = wm <= 1 ? 1 : wm <= 2 ? 2 : wm <= 4 ? 4 : 8;
     const int ndw = (g.nmax + 63) / 64, ngw = std::max((g.gmax + 63) / 64, 1);
     int words = ((g.nmax * g.wmax) + 1) & ~1;
-    words += 2 * ndw + 2 * ndw + 2 * ngw + ((g.nmax + 1) & ~1) + 32;
+    words += 2 * ndw + 2 * ndw + 2 * ngw + ((g.nmax + 1) & ~1) + (g.gac ? SCRATCH_GAC_WORDS : SCRATCH_WORDS);
     g.lds_words = (words + 1) & ~1;
     return g;
 }
@@ -628,6 +638,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG, use_var);
     int wpb = use_var ? 8 : 4;
     // learned search: each worker also keeps its task's static features [n][4]
+    // (placed before the scratch words, which stay last)
     const int lds_words = G.lds_words + (feat == 1 ? 4 * G.nmax : 0);
     const size_t per_wave = (size_t)lds_words * 4;
     const size_t pol_bytes = feat == 1 ? (size_t)POLICY_LDS_WORDS * 4 : 0;  // network copy

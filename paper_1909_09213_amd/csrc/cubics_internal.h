@@ -14,7 +14,10 @@ enum UnitType : int32_t {
     U_LT_LB = 4,   // keep a >= min(D_src) - p0 + 1
     U_QUEENS = 5,  // p0 = k, p1 = delta: a conflicts with b iff a - b - delta in {0, k, -k}
 };
-enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2 };
+enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2, G_ALLDIFF_GAC = 3 };
+constexpr int GAC_MAX_K = 64;     // variables of one GAC all-different (one lane each)
+constexpr int SCRATCH_WORDS = 32;      // per-worker LDS scratch
+constexpr int SCRATCH_GAC_WORDS = 96;  // ... when a GAC all-different is present
 // VAR layout pair entry, one word (type << 28) | param: TABLE param = word
 // offset of the rows indexed by the source value; NEQ / LT param = delta
 // (28-bit signed); QUEENS param = k << 15 | (delta & 0x7FFF).

@@ -518,6 +518,184 @@ DEV bool revise_alldiff(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt
     return fail;
 }
 
+// Readlane of a 64-bit lane value from a uniform lane index.
+DEV u64 readlane64(u64 v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+
+template <int WM>
+DEV bool bit_of(const uint32_t (&d)[WM], int v) {
+    bool r = false;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) r |= (w == (v >> 5)) && ((d[w] >> (v & 31)) & 1u);
+    return r;
+}
+
+// All-different to generalized arc consistency (Regin's method), one lane
+// per scope variable (k <= 64), domains aligned in value space.
+//  1. A matching covering the scope: for each variable in turn, a
+//     breadth-first search for an augmenting path over value bitsets (layer
+//     = values reachable through the previous layer's matched variables);
+//     none -> the constraint has no solution.
+//  2. With M(x) the value of x, value u points to M(x) when u is in D_x.
+//     (x, v) belongs to some solution iff v = M(x), or v is reachable from
+//     an unmatched value, or v = M(y) with y reachable from x in the graph
+//     x -> y when M(x) is in D_y (both ends on one alternating cycle).
+// Scratch (LDS bytes): par[32 WM] the variable through which a value was
+// reached, then mv[64] the matched value of each variable.
+template <int WM>
+DEV bool revise_alldiff_gac(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt, Counters &C, int lane) {
+    const int W = I.W, k = g.k, base = g.coef_off;
+    const int32_t *sc = I.gscope + g.scope_off;
+    uint8_t *par = (uint8_t *)L.scr;
+    uint8_t *mv = par + 32 * WM;
+    const bool act = lane < k;
+    const int v = act ? sc[lane] : 0;
+    const int sft = act ? I.lo[v] - base : 0;
+    uint32_t d[WM], Dv[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) d[w] = (act && w < W) ? L.dom[v * W + w] : 0u;
+    if (sft) {
+        shl_w(d, sft, Dv);
+    } else {
+#pragma unroll
+        for (int w = 0; w < WM; ++w) Dv[w] = d[w];
+    }
+    C.rev += lane == 0 ? 1 : 0;
+    C.bytes += lane == 0 ? 4ull * (u64)k * W : 0ull;
+    if (__ballot(act && pop_w(Dv, WM) == 0)) return true;
+
+    // ---- 1. matching
+    int M = -1;
+    uint32_t used[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) used[w] = 0u;
+    for (int x = 0; x < k; ++x) {
+        uint32_t F[WM], Vis[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            F[w] = (uint32_t)__builtin_amdgcn_readlane((int)Dv[w], x);
+            Vis[w] = F[w];
+        }
+        for (int t = lane; t < 32 * WM; t += 64)
+            if (bit_of<WM>(F, t)) par[t] = (uint8_t)x;
+        wsync();
+        int found = -1;
+        for (;;) {
+#pragma unroll
+            for (int w = WM - 1; w >= 0; --w) {
+                const uint32_t fr = F[w] & ~used[w];
+                if (fr) found = 32 * w + __ffs(fr) - 1;
+            }
+            if (found >= 0) break;
+            const bool on = act && M >= 0 && bit_of<WM>(F, M);
+            uint32_t NF[WM];
+            bool any = false;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                NF[w] = wave_or(on ? (Dv[w] & ~Vis[w]) : 0u);
+                any |= NF[w] != 0u;
+            }
+            if (!any) return true;  // x cannot be matched: no solution
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                uint32_t bits = on ? (Dv[w] & NF[w]) : 0u;
+                while (bits) {
+                    par[32 * w + __ffs(bits) - 1] = (uint8_t)lane;
+                    bits &= bits - 1;
+                }
+                Vis[w] |= NF[w];
+                F[w] = NF[w];
+            }
+            wsync();
+        }
+        // augment: walk back from the free value to x, shifting the matches
+        int val = found;
+        for (;;) {
+            const int y = uni((int)par[val]);
+            const int prev = __builtin_amdgcn_readlane(M, y);
+            if (lane == y) M = val;
+            if (y == x) break;
+            val = prev;
+        }
+#pragma unroll
+        for (int w = 0; w < WM; ++w)
+            if (w == (found >> 5)) used[w] |= 1u << (found & 31);
+        wsync();
+    }
+
+    // ---- 2. values reachable from unmatched values
+    uint32_t R[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) R[w] = wave_or(Dv[w]) & ~used[w];
+    for (;;) {
+        bool hit = false;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) hit |= (Dv[w] & R[w]) != 0u;
+        const bool add = act && hit && !bit_of<WM>(R, M);
+        if (__ballot(add) == 0ull) break;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) R[w] |= wave_or((add && (M >> 5) == w) ? (1u << (M & 31)) : 0u);
+    }
+    // ---- 3. reachability between variables (transitive closure)
+    u64 inn = 0;  // on lane y: variables a != y with M(a) in D_y
+    for (int a = 0; a < k; ++a) {
+        const int ma = __builtin_amdgcn_readlane(M, a);
+        if (act && a != lane && bit_of<WM>(Dv, ma)) inn |= 1ull << a;
+    }
+    u64 out = 0;  // on lane x: variables y with x -> y
+    for (int y = 0; y < k; ++y) {
+        const u64 iy = readlane64(inn, y);
+        if ((iy >> lane) & 1ull) out |= 1ull << y;
+    }
+    for (int z = 0; z < k; ++z) {
+        const u64 oz = readlane64(out, z);
+        if ((out >> z) & 1ull) out |= oz;
+    }
+    if (act) mv[lane] = (uint8_t)M;
+    wsync();
+    // ---- 4. keep = M(x), reachable values, matched values of reachable variables
+    uint32_t K[WM];
+#pragma unroll
+    for (int w = 0; w < WM; ++w) K[w] = R[w] | ((act && (M >> 5) == w) ? (1u << (M & 31)) : 0u);
+    {
+        u64 o = act ? out : 0ull;
+        while (o) {
+            const int y = __ffsll((long long)o) - 1;
+            o &= o - 1;
+            const int my = mv[y];
+#pragma unroll
+            for (int w = 0; w < WM; ++w)
+                if (w == (my >> 5)) K[w] |= 1u << (my & 31);
+        }
+    }
+    bool ch = false;
+#pragma unroll
+    for (int w = 0; w < WM; ++w) {
+        const uint32_t nv = Dv[w] & K[w];
+        ch |= nv != Dv[w];
+        Dv[w] = nv;
+    }
+    if (act && ch) {
+        uint32_t nd[WM];
+        if (sft) {
+            shr_w(Dv, sft, nd);
+        } else {
+#pragma unroll
+            for (int w = 0; w < WM; ++w) nd[w] = Dv[w];
+        }
+#pragma unroll
+        for (int w = 0; w < WM; ++w)
+            if (w < W) L.dom[v * W + w] = nd[w];
+        atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+        C.bytes += 4ull * W;
+    }
+    wsync();
+    return false;
+}
+
 DEV long long floor_div(long long a, long long b) {  // b > 0
     long long q = a / b;
     if ((a % b != 0) && (a < 0)) --q;
@@ -641,8 +819,9 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
                     const int gi = w * 64 + __ffsll((long long)bits) - 1;
                     bits &= bits - 1;
                     const GDesc g = I.gdesc[gi];
-                    const bool f = g.type == G_ALLDIFF ? revise_alldiff<WM>(I, g, L, nxt, C, lane)
-                                                       : revise_linear<WM>(I, g, L, nxt, C, lane);
+                    const bool f = g.type == G_ALLDIFF  ? revise_alldiff<WM>(I, g, L, nxt, C, lane)
+                                   : g.type == G_LINEAR ? revise_linear<WM>(I, g, L, nxt, C, lane)
+                                                        : revise_alldiff_gac<WM>(I, g, L, nxt, C, lane);
                     if (f) return true;
                 }
             }
@@ -1731,8 +1910,12 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     off += 2 * (ngw > 0 ? ngw : 1);
     L.fails = base + off;
     off += (P.nmax + 1) & ~1;
-    L.scr = base + off;
-    L.feat = FEAT == 1 ? (float *)(base + off + 32) : nullptr;
+    L.feat = nullptr;
+    if (FEAT == 1) {  // the learned search's copy of the task's static features
+        L.feat = (float *)(base + off);
+        off += 4 * P.nmax;
+    }
+    L.scr = base + off;  // the rest of the worker's words
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
     const long long t_start = (long long)wall_clock64();
     Counters C = {};
