@@ -198,3 +198,22 @@ def test_autotune_then_auto_layout(ctx, cb):
     ref = oracle.solve(inst, oracle.MODE_COUNT)
     r = ctx.solve(p, cb.MODE_COUNT)
     assert (r.count, r.nodes) == (ref.count, ref.nodes)
+
+
+def test_host_cancel_stops_a_running_solve(ctx, cb):
+    """cubics_cancel from another thread: the persistent kernel sees the
+    pinned flag at its next poll and the solve returns CANCELLED early."""
+    import threading
+    import time
+    p = ctx.load(cspgen.rb(0).fix({0: 0}))  # ~4e10 nodes: tens of seconds uncancelled
+    timer = threading.Timer(0.5, ctx.cancel)
+    timer.start()
+    t0 = time.perf_counter()
+    r = ctx.solve(p, cb.MODE_COUNT)
+    dt = time.perf_counter() - t0
+    timer.join()
+    _say(f"cancelled after {dt:.2f} s, {r.nodes} nodes")
+    assert r.verdict == "CANCELLED" and dt < 5.0
+    # the next solve on the context starts with the flag cleared
+    q = ctx.solve(ctx.load(cspgen.queens(8)), cb.MODE_COUNT)
+    assert q.verdict == "SAT" and q.count == 92
