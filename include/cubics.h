@@ -230,7 +230,8 @@ int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
    counts (the occupancy-limited maximum divided by 1, 2 and 4: a small
    search tree finishes sooner on fewer workers, whose idle polls and task
    hand-offs cost less), measure search nodes per ms, and remember the fastest
-   pair for the first problem's shape bucket (domain words, domain size,
+   pair (a smaller worker count of the same layout must be 5% faster to win)
+   for the first problem's shape bucket (domain words, domain size,
    variable count, constraint kinds).  Later solves with layout AUTO and
    workers 0 on the same context use it.  *chosen and *chosen_div (nullable)
    receive the layout and the divisor; rates (nullable, host,

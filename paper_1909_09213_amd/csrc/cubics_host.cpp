@@ -862,7 +862,10 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
             for (int b = 0; b < B; ++b) nodes += res[b].nodes;
             const double rate = (double)nodes / std::max(res[0].kernel_ms, 1e-3);
             if (rates) rates[(cands[ci] - 1) * CUBICS_AUTOTUNE_DIVS + di] = rate;
-            if (rate > best_rate) {
+            // fewer workers must be clearly faster (5%) to win: rates within
+            // run-to-run noise keep the fuller launch
+            const double need = (best_rate > 0 && di > 0 && cands[ci] == best.layout) ? 1.05 : 1.0;
+            if (rate > best_rate * need) {
                 best_rate = rate;
                 best = {cands[ci], divs[di]};
             }

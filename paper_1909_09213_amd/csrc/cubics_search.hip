@@ -1630,6 +1630,12 @@ DEV int node_test_var(int n, uint32_t d, int lane, int *bx) {
     return 1;
 }
 
+// The trail of the VAR layout: every frame's domain snapshot (one word per
+// lane) goes to HBM, but the frames' branching variable, depth and untried
+// values stay in registers, frame f on lane f (at most n <= 64 frames: the
+// variables branched on along a path are distinct).  Exhausted frames are
+// popped without a memory access; the snapshot of the frame below the top
+// is prefetched into a register, so that returning one level needs no wait.
 template <int WM>
 DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                       Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
@@ -1637,14 +1643,16 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
     const int n = I.n;
     const uint32_t FW = P.frame_words;
     int sp = 0;
-    Frame<WM> F;
+    Frame<WM> F;  // the top frame (sp - 1)
     bool have_open = false, need_restore = false;
     int depth = F0.depth;
     int since_poll = 0;
     int open_x = 0;
     uint32_t d = lane < n ? L.dom[lane] : 0u;
-    uint32_t snapc = 0u;
-    bool snap_valid = false;
+    uint32_t snapc = 0u, snapp = 0u;  // snapshots of frames sp - 1 and sp - 2
+    bool snap_valid = false, snapp_valid = false;
+    int mx = 0, mdep = 0;  // frame `lane` (below the top): variable, depth
+    uint32_t mval = 0u;    // ... and its untried values
 
     if (kind == K_ROOT) {
         for (int t = 0; t < I.n_unary; ++t) {
@@ -1672,7 +1680,6 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
         if (lane < n) trail[FRAME_HDR + lane] = d;
         snapc = d;
         snap_valid = true;
-        frame_store_meta<WM>(trail, F, lane);
         sp = 1;
     }
 
@@ -1707,10 +1714,17 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 dx = rem;
             }
             {
-                if (sp > 0 && lane == 0) trail[(size_t)(sp - 1) * FW + 4] = F.v[0];
+                // the outgoing top frame's meta moves to its lane
+                if (sp > 0 && lane == sp - 1) {
+                    mx = F.x;
+                    mdep = F.depth;
+                    mval = F.v[0];
+                }
                 uint32_t *f = trail + (size_t)sp * FW;
                 if (lane < n) f[FRAME_HDR + lane] = d;
                 C.ubytes += 4ull * n;
+                snapp = snapc;
+                snapp_valid = snap_valid;
                 snapc = d;
                 snap_valid = true;
                 F.x = x;
@@ -1718,22 +1732,39 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 F.v[0] = dx;
 #pragma unroll
                 for (int k = 1; k < WM; ++k) F.v[k] = 0u;
-                frame_store_meta<WM>(f, F, lane);
                 ++sp;
                 need_restore = false;
             }
         }
     next_child:
-        for (;;) {
-            if (sp == 0) return;
-            if (F.v[0] == 0u) {
+        {
+            // pop exhausted frames (registers only)
+            int popped = 0;
+            while (sp > 0 && F.v[0] == 0u) {
                 --sp;
-                if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
-                need_restore = true;
-                snap_valid = false;
-                continue;
+                ++popped;
+                if (sp > 0) {
+                    F.x = __builtin_amdgcn_readlane(mx, sp - 1);
+                    F.depth = __builtin_amdgcn_readlane(mdep, sp - 1);
+                    F.v[0] = (uint32_t)__builtin_amdgcn_readlane((int)mval, sp - 1);
+                }
             }
-            break;
+            if (sp == 0) return;
+            if (popped) {
+                need_restore = true;
+                if (popped == 1 && snapp_valid) {
+                    snapc = snapp;
+                    snap_valid = true;
+                } else {
+                    snap_valid = false;
+                }
+                // prefetch the snapshot of the frame below the new top
+                snapp_valid = false;
+                if (sp >= 2) {
+                    snapp = lane < n ? trail[(size_t)(sp - 2) * FW + FRAME_HDR + lane] : 0u;
+                    snapp_valid = true;
+                }
+            }
         }
         {
             const int vi = __ffs(F.v[0]) - 1;
@@ -1805,22 +1836,25 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
             }
             idle = uni(idle);
             if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
-                int tsel = -1;
-                for (int base = 0; base < sp - 1 && tsel < 0; base += 64) {
-                    const int t = base + lane;
-                    const bool nz = t < sp - 1 && trail[(size_t)t * FW + 4] != 0u;
-                    const u64 m = __ballot(nz);
-                    if (m) tsel = base + __ffsll((long long)m) - 1;
-                }
+                // donate the shallowest frame that still has untried values
+                const u64 m = __ballot(lane < sp - 1 && mval != 0u);
+                int tsel = m ? __ffsll((long long)m) - 1 : -1;
                 if (tsel < 0 && F.v[0] != 0u) tsel = sp - 1;
                 if (tsel >= 0) {
                     uint32_t *f = trail + (size_t)tsel * FW;
                     Frame<WM> D;
-                    frame_load_meta<WM>(f, D);
-                    if (tsel == sp - 1) D = F;
+                    if (tsel == sp - 1) {
+                        D = F;
+                    } else {
+                        D.x = __builtin_amdgcn_readlane(mx, tsel);
+                        D.depth = __builtin_amdgcn_readlane(mdep, tsel);
+                        D.v[0] = (uint32_t)__builtin_amdgcn_readlane((int)mval, tsel);
+#pragma unroll
+                        for (int k = 1; k < WM; ++k) D.v[k] = 0u;
+                    }
                     if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, n, lane)) {
-                        if (lane == 0) f[4] = 0u;
                         if (tsel == sp - 1) F.v[0] = 0u;
+                        else if (lane == tsel) mval = 0u;
                         C.steals += 1;
                     }
                 }

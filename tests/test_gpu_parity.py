@@ -194,7 +194,8 @@ def test_autotune_then_auto_layout(ctx, cb):
     chosen, div, rates = ctx.autotune([p], cb.MODE_COUNT, time_ms=30, rates=True)
     # n = 40 <= 64, one word per domain: every layout admitted
     assert {lay for lay, _ in rates} == {1, 2, 3}
-    assert rates[(chosen, div)] == max(rates.values())
+    # the fastest pair, or one of the same layout with more workers within 5%
+    assert rates[(chosen, div)] * 1.05 >= max(rates.values())
     ref = oracle.solve(inst, oracle.MODE_COUNT)
     r = ctx.solve(p, cb.MODE_COUNT)
     assert (r.count, r.nodes) == (ref.count, ref.nodes)
