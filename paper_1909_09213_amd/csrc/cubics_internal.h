@@ -87,10 +87,16 @@ struct QCtl {
     uint32_t head; uint32_t _p0[31];
     uint32_t tail; uint32_t _p1[31];
     int32_t pending; int32_t _p2[31];
-    int32_t idle; int32_t _p3[31];
+    // idle workers (bits 0..23) | SIG_DONE | SIG_STOP: the one word a busy
+    // worker polls; the rest is read only when it is non-zero
+    uint32_t signal; int32_t _p3[31];
     unsigned long long produced; uint32_t _p4[30];
     int32_t stop; int32_t stop_reason; uint32_t _p5[30];
 };
+
+constexpr uint32_t SIG_IDLE_MASK = 0x00FFFFFFu;
+constexpr uint32_t SIG_DONE = 1u << 29;  // some instance's done flag is set
+constexpr uint32_t SIG_STOP = 1u << 30;  // the whole launch stops
 
 // Queue slot / trail frame header layout (uint32 words).
 constexpr int SLOT_HDR = 16;   // [0] inst [1] kind [2] x [3] depth [4..12) vals

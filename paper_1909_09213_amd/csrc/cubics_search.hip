@@ -103,6 +103,12 @@ DEV void st_rel_i(int32_t *p, int v) {
 DEV int add_i(int32_t *p, int v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+DEV uint32_t add_u(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+DEV uint32_t or_u(uint32_t *p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 DEV void st_rlx(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -1014,6 +1020,7 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
                 add_u64(&ctl->count, 1ull);
                 ctl->reason = 1;
                 st_rel_i(&ctl->done, 1);
+                or_u(&P.q->signal, SIG_DONE);
             }
         }
         return;
@@ -1035,6 +1042,7 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
         if (I.max_solutions && slot + 1 >= I.max_solutions && lane == 0) {
             ctl->reason = 3;
             st_rel_i(&ctl->done, 1);
+            or_u(&P.q->signal, SIG_DONE);
         }
     } else {
         C.sols += 1;
@@ -1198,7 +1206,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     uint32_t snapc[NC];
     bool snap_valid = false;
     int depth = F0.depth;
-    int since_poll = 0;
+    int since_poll = 0, polls = 0;
     int open_x = 0;
     const bool tracing = FEAT == 2 && P.trace_out != nullptr;
     const bool learned = FEAT == 1 && P.branching == 1;
@@ -1418,14 +1426,16 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         // periodic checks: stop flags, limits, donation
         if (++since_poll >= POLL) {
             since_poll = 0;
+            // one shared word per poll; stop, done and queue words only when
+            // it says so
             int stop = 0, idle = 0;
             u64 qlen = 0;
             if (lane == 0) {
-                stop = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
-                if (P.donate) {
-                    idle = ld_rlx_i(&P.q->idle);
-                    qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
-                }
+                const uint32_t sig = ld_rlx(&P.q->signal);
+                stop = (sig & SIG_STOP) ? 1 : ((sig & SIG_DONE) ? ld_rlx_i(&ctl->done) : 0);
+                idle = (int)(sig & SIG_IDLE_MASK);
+                if (P.donate && idle > 0) qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
+                else idle = 0;
             }
             stop = uni(stop);
             if (stop) return;
@@ -1435,16 +1445,22 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 tot = uni64(tot);
                 C.nodes = 0;
                 if (tot >= I.max_nodes) {
-                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); }
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); or_u(&P.q->signal, SIG_DONE); }
                     return;
                 }
             }
-            if (P.time_ticks || P.cancel) {
+            // the clock and the host's cancel flag (a read over PCIe) every
+            // 16th poll
+            if ((P.time_ticks || P.cancel) && (++polls & 15) == 0) {
                 int st2 = 0;
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
                     if (P.cancel && *P.cancel) st2 = 3;
-                    if (st2) { P.q->stop_reason = st2; st_rel_i(&P.q->stop, 1); }
+                    if (st2) {
+                        P.q->stop_reason = st2;
+                        st_rel_i(&P.q->stop, 1);
+                        or_u(&P.q->signal, SIG_STOP);
+                    }
                 }
                 if (uni(st2)) return;
             }
@@ -1646,7 +1662,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
     Frame<WM> F;  // the top frame (sp - 1)
     bool have_open = false, need_restore = false;
     int depth = F0.depth;
-    int since_poll = 0;
+    int since_poll = 0, polls = 0;
     int open_x = 0;
     uint32_t d = lane < n ? L.dom[lane] : 0u;
     uint32_t snapc = 0u, snapp = 0u;  // snapshots of frames sp - 1 and sp - 2
@@ -1805,14 +1821,16 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
         if (++since_poll >= POLL) {
             fold_var(C);
             since_poll = 0;
+            // one shared word per poll; stop, done and queue words only when
+            // it says so
             int stop = 0, idle = 0;
             u64 qlen = 0;
             if (lane == 0) {
-                stop = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
-                if (P.donate) {
-                    idle = ld_rlx_i(&P.q->idle);
-                    qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
-                }
+                const uint32_t sig = ld_rlx(&P.q->signal);
+                stop = (sig & SIG_STOP) ? 1 : ((sig & SIG_DONE) ? ld_rlx_i(&ctl->done) : 0);
+                idle = (int)(sig & SIG_IDLE_MASK);
+                if (P.donate && idle > 0) qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
+                else idle = 0;
             }
             if (uni(stop)) return;
             if (I.max_nodes) {
@@ -1821,16 +1839,22 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 tot = uni64(tot);
                 C.nodes = 0;
                 if (tot >= I.max_nodes) {
-                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); }
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); or_u(&P.q->signal, SIG_DONE); }
                     return;
                 }
             }
-            if (P.time_ticks || P.cancel) {
+            // the clock and the host's cancel flag (a read over PCIe) every
+            // 16th poll
+            if ((P.time_ticks || P.cancel) && (++polls & 15) == 0) {
                 int st2 = 0;
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
                     if (P.cancel && *P.cancel) st2 = 3;
-                    if (st2) { P.q->stop_reason = st2; st_rel_i(&P.q->stop, 1); }
+                    if (st2) {
+                        P.q->stop_reason = st2;
+                        st_rel_i(&P.q->stop, 1);
+                        or_u(&P.q->signal, SIG_STOP);
+                    }
                 }
                 if (uni(st2)) return;
             }
@@ -1966,7 +1990,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         if (!got) {
             int pend = 0;
             if (lane == 0) {
-                if (!idle) add_i(&P.q->idle, 1);
+                if (!idle) add_u(&P.q->signal, 1u);
                 pend = ld_rlx_i(&P.q->pending);
             }
             idle = true;
@@ -1977,7 +2001,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         }
         backoff = 1;
         if (idle) {
-            if (lane == 0) add_i(&P.q->idle, -1);
+            if (lane == 0) add_u(&P.q->signal, 0xFFFFFFFFu);  // idle - 1
             idle = false;
         }
         cell = uniu(cell);
@@ -2002,7 +2026,10 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         if (lane == 0) st_rlx(&P.qseq[cell], pos + P.qmask + 1u);
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
-        if (lane == 0) skip = ld_rlx_i(&ctl->done) | ld_rlx_i(&P.q->stop);
+        if (lane == 0) {
+            const uint32_t sig = ld_rlx(&P.q->signal);
+            skip = (sig & SIG_STOP) ? 1 : ((sig & SIG_DONE) ? ld_rlx_i(&ctl->done) : 0);
+        }
         if (!uni(skip)) {
             if (VAR)
                 run_task_var<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
@@ -2013,7 +2040,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         flush<WM>(ctl, C, lane);
         if (lane == 0) add_i(&P.q->pending, -1);
     }
-    if (lane == 0 && idle) add_i(&P.q->idle, -1);
+    if (lane == 0 && idle) add_u(&P.q->signal, 0xFFFFFFFFu);
 }
 
 #if CUBICS_ONLY_WM == 1
@@ -2058,7 +2085,7 @@ __global__ void init_kernel(SearchParams P) {
         P.q->head = 0;
         P.q->tail = (uint32_t)P.B;
         P.q->pending = P.B;
-        P.q->idle = 0;
+        P.q->signal = 0u;
         P.q->produced = 0;
         P.q->stop = 0;
         P.q->stop_reason = 0;
