@@ -61,6 +61,9 @@ def _load():
         lib.orc_solve.argtypes = [PP, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_Stats)]
         lib.orc_solve.restype = ctypes.c_int
+        lib.orc_solve2.argtypes = [PP, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(_Stats)]
+        lib.orc_solve2.restype = ctypes.c_int
         lib.orc_root.argtypes = [PP, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         lib.orc_root.restype = ctypes.c_int
         lib.orc_verify.argtypes = [PP, ctypes.c_void_p]
@@ -110,13 +113,15 @@ class Result:
 
 
 def solve(inst, mode: int = MODE_COUNT, max_nodes: int = 0, cap: int = 0,
-          sol_cap: int = 0) -> Result:
+          sol_cap: int = 0, two_way: bool = False) -> Result:
+    """two_way: 2-way branching (x = min D_x, then x != min D_x)."""
     lib = _load()
     P, keep = _problem(inst)
     sols = np.zeros((max(sol_cap, 0), max(inst.n, 1)), dtype=np.int32)
     st = _Stats()
-    r = lib.orc_solve(ctypes.byref(P), mode, max_nodes, cap,
-                      sols.ctypes.data if sol_cap > 0 else None, sol_cap, ctypes.byref(st))
+    r = lib.orc_solve2(ctypes.byref(P), mode, max_nodes, cap,
+                       sols.ctypes.data if sol_cap > 0 else None, sol_cap, 1 if two_way else 0,
+                       ctypes.byref(st))
     if r != 0:
         raise ValueError("oracle: malformed instance")
     return Result(VERDICTS[st.verdict], st.count, st.n_written, st.nodes, st.fails,

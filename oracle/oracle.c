@@ -82,6 +82,7 @@ typedef struct {
     unsigned char *inq;
     /* search */
     int mode;
+    int two_way;  /* 1: children x = min D_x, then x != min D_x */
     int64_t max_nodes, cap;
     int32_t *sols;
     int64_t sol_cap;
@@ -407,6 +408,26 @@ static void dfs(ctx_t *C, unsigned char *D, int depth, unsigned char *chg) {
     int x = choose_var(C, D);
     size_t bytes = (size_t)C->n * (size_t)C->dmax;
     unsigned char *child = (unsigned char *)malloc(bytes);
+    if (C->two_way) {
+        /* 2-way branching: x = a with a the smallest value, then x != a */
+        int a = dom_min(C, D, x);
+        for (int side = 0; side < 2 && !C->stop; ++side) {
+            if (C->max_nodes > 0 && C->st.nodes >= C->max_nodes) { C->stop = 3; break; }
+            memcpy(child, D, bytes);
+            if (side == 0) {
+                memset(child + (int64_t)x * C->dmax, 0, (size_t)C->dmax);
+                child[(int64_t)x * C->dmax + a] = 1;
+            } else {
+                child[(int64_t)x * C->dmax + a] = 0;
+            }
+            C->st.nodes++;
+            enqueue_var(C, x);
+            if (propagate(C, child, chg)) { C->st.fails++; continue; }
+            dfs(C, child, depth + 1, chg);
+        }
+        free(child);
+        return;
+    }
     for (int v = 0; v < C->P->dsize[x] && !C->stop; ++v) {
         if (!D[(int64_t)x * C->dmax + v]) continue;
         if (C->max_nodes > 0 && C->st.nodes >= C->max_nodes) { C->stop = 3; break; }
@@ -515,12 +536,15 @@ static int root_fixpoint(ctx_t *C, unsigned char *D, unsigned char *chg) {
 /* ------------------------------------------------------------ exported */
 
 /* Full search.  mode: 0 first, 1 all (store up to sol_cap), 2 count.
-   max_nodes / cap: 0 = unlimited.  Returns 0, or -1 on malformed input. */
-int orc_solve(const orc_problem *P, int mode, int64_t max_nodes, int64_t cap,
-              int32_t *sols, int64_t sol_cap, orc_stats *out) {
+   max_nodes / cap: 0 = unlimited.  two_way: 2-way branching (x = min D_x,
+   then x != min D_x) instead of one child per value.  Returns 0, or -1 on
+   malformed input. */
+int orc_solve2(const orc_problem *P, int mode, int64_t max_nodes, int64_t cap,
+               int32_t *sols, int64_t sol_cap, int two_way, orc_stats *out) {
     ctx_t C;
     if (setup(&C, P)) { teardown(&C); return -1; }
     C.mode = mode;
+    C.two_way = two_way != 0;
     C.max_nodes = max_nodes;
     C.cap = cap;
     C.sols = sols;
@@ -540,6 +564,12 @@ int orc_solve(const orc_problem *P, int mode, int64_t max_nodes, int64_t cap,
     free(D); free(chg);
     teardown(&C);
     return 0;
+}
+
+/* d-way labeling (the default reading). */
+int orc_solve(const orc_problem *P, int mode, int64_t max_nodes, int64_t cap,
+              int32_t *sols, int64_t sol_cap, orc_stats *out) {
+    return orc_solve2(P, mode, max_nodes, cap, sols, sol_cap, 0, out);
 }
 
 /* Root fixpoint as n x W bit words (bit a = value lo_i + a).

@@ -68,6 +68,9 @@ def test_worked_example(form):
     assert _canon(r.solutions) == _canon(bsols)
     f = oracle.solve(inst, oracle.MODE_FIRST, sol_cap=1)
     assert f.verdict == "SAT" and f.solutions[0].tolist() == g["first"]
+    t = oracle.solve(inst, oracle.MODE_ALL, sol_cap=64, two_way=True)
+    assert t.count == g["count"][0] and _canon(t.solutions) == _canon(bsols)
+    assert t.nodes == g["nodes_two_way"][0] and t.fails == 0
 
 
 # ------------------------------------------------------------------ queens
@@ -429,9 +432,9 @@ def _def_fixpoint(inst, D):
     return D
 
 
-def _def_search(inst):
-    """Independent d-way first-fail search over _def_fixpoint: returns
-    (count, nodes, fails)."""
+def _def_search(inst, two_way=False):
+    """Independent first-fail search over _def_fixpoint, d-way or 2-way
+    (x = min D_x, then x != min D_x): returns (count, nodes, fails)."""
     D0 = []
     for i in range(inst.n):
         vals = set(int(inst.lo[i]) + a for a in range(int(inst.dsize[i])))
@@ -448,9 +451,11 @@ def _def_search(inst):
             stats["count"] += 1
             return
         x = min((len(D[i]), i) for i in range(inst.n) if len(D[i]) >= 2)[1]
-        for v in sorted(D[x]):
+        a = min(D[x])
+        doms = [{a}, D[x] - {a}] if two_way else [{v} for v in sorted(D[x])]
+        for dx in doms:
             child = [set(s) for s in D]
-            child[x] = {v}
+            child[x] = dx
             stats["nodes"] += 1
             r = _def_fixpoint(inst, child)
             if r is None:
@@ -615,3 +620,20 @@ def test_gac_alldiff_counts_and_nodes():
     g = cspgen.global_twin(1)
     assert oracle.solve(g.with_gac(), oracle.MODE_COUNT).count == oracle.solve(g, oracle.MODE_COUNT).count
     assert fewer > 0
+
+
+def test_two_way_branching_counts_and_nodes():
+    """2-way branching: the same solutions, node counts equal to the
+    independent 2-way search."""
+    for idx in range(50):
+        inst = cspgen.mixed(idx + 1300, n=5, dmax=5, m=6)
+        a = oracle.solve(inst, oracle.MODE_COUNT)
+        b = oracle.solve(inst, oracle.MODE_COUNT, two_way=True)
+        assert a.count == b.count, idx
+        s = _def_search(inst, two_way=True)
+        assert (b.count, b.nodes, b.fails) == (s["count"], s["nodes"], s["fails"]), idx
+    for n in range(4, 8):
+        inst = cspgen.queens(n)
+        b = oracle.solve(inst, oracle.MODE_COUNT, two_way=True)
+        s = _def_search(inst, two_way=True)
+        assert (b.count, b.nodes, b.fails) == (s["count"], s["nodes"], s["fails"]), n
