@@ -128,6 +128,10 @@ typedef struct {
     int32_t use_graph;       /* 1 = capture the launch sequence (queue reset + persistent
                                 search) in a hipGraph on first use and replay it on later
                                 calls with identical launch parameters */
+    int32_t two_way;         /* 0 = d-way labeling (one child per value, ascending);
+                                1 = 2-way branching: x = a, then x != a, with a the
+                                smallest value of the branching variable (the same
+                                solutions, another tree: other node counts) */
 } cubics_limits;
 
 typedef struct {

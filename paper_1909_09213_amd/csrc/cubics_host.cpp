@@ -102,6 +102,7 @@ struct cubics_prob {
     InstDev dev;  // with device pointers into blob
     int n = 0, W = 1, dmax = 1;
     int n_units = 0, n_glob = 0;
+    int64_t dsum = 0;  // sum over variables of (dsize - 1): bounds 2-way branchings on a path
     bool has_table = false;
     bool has_gac = false;  // a GAC all-different (needs the larger LDS scratch)
     std::string bucket;
@@ -470,6 +471,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     p->n_glob = (int)gdesc.size();
     p->has_table = has_table;
     p->has_gac = has_gac;
+    for (int i = 0; i < n; ++i) p->dsum += dsize[i] - 1;
     char *b8 = (char *)blob;
     InstDev &I = p->dev;
     memset(&I, 0, sizeof I);
@@ -608,6 +610,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const cubics_limits &L0 = lims ? lims[0] : dflt;
     if (L0.branching == CUBICS_BRANCH_LEARNED && !L0.policy)
         return fail(CUBICS_EINVAL, "LEARNED branching needs a policy");
+    if (L0.two_way != 0 && L0.two_way != 1) return fail(CUBICS_EINVAL, "two_way must be 0 or 1");
     if (L0.branching != CUBICS_BRANCH_FIRST_FAIL && L0.branching != CUBICS_BRANCH_LEARNED)
         return fail(CUBICS_EINVAL, "bad branching %d", L0.branching);
     if (L0.split_target < 0 || L0.time_ms < 0 || L0.workers < 0)
@@ -626,6 +629,14 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     }
     const Geometry G = geometry(probs, B);
     const int layout = choose_layout(probs, B, L0.layout);
+    // trail frames a path can need: one per branching plus a task's frame 0.
+    // d-way assigns a variable per branching (<= n + 1 frames); 2-way may
+    // branch on a variable again after x != a, at most dsize - 1 times
+    int64_t frames = G.nmax + 1;
+    if (L0.two_way) {
+        frames = 2;
+        for (int b = 0; b < B; ++b) frames = std::max<int64_t>(frames, 1 + probs[b]->dsum);
+    }
 
     // ---- workers: fill the device with co-resident wavefronts.  A single
     // instance whose packed tables fit is staged in LDS once per workgroup;
@@ -634,7 +645,8 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
     bool var_all = G.wmax == 1;
     for (int b = 0; b < B && var_all; ++b) var_all = probs[b]->dev.var_ok != 0;
-    const bool use_var = feat == 0 && layout == CUBICS_LAYOUT_VAR && var_all;
+    // (the VAR layout keeps the frames' meta in lane registers: 64 frames)
+    const bool use_var = feat == 0 && layout == CUBICS_LAYOUT_VAR && var_all && frames <= 64;
     const int variant = search_variant(feat, G.gmax > 0, layout == CUBICS_LAYOUT_SEG, use_var);
     int wpb = use_var ? 8 : 4;
     // learned search: each worker also keeps its task's static features [n][4]
@@ -661,12 +673,18 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         if (it != ctx->tuned.end()) div = it->second.div;
     }
     int nworkers = L0.workers > 0 && worker_div == 0 ? L0.workers : std::max(1, bpc * wpb * ctx->cu_count / div);
-    const int blocks = (nworkers + wpb - 1) / wpb;
 
     // ---- buffers
     const uint32_t frame_words = (uint32_t)((FRAME_HDR + G.nmax * G.wmax + 15) / 16 * 16);
     const uint32_t slot_words = (uint32_t)((SLOT_HDR + G.nmax * G.wmax + 15) / 16 * 16);
-    const uint32_t trail_words = frame_words * (uint32_t)(G.nmax + 1);
+    const int64_t trail_words64 = (int64_t)frame_words * frames;
+    if (trail_words64 > (1LL << 28))
+        return fail(CUBICS_EUNSUPPORTED, "a worker's trail would need %lld frames of %u words", (long long)frames,
+                    frame_words);
+    const uint32_t trail_words = (uint32_t)trail_words64;
+    // at most 16 GiB of trail stacks: fewer workers for very deep trails
+    nworkers = (int)std::min<int64_t>(nworkers, std::max<int64_t>(1, (16LL << 30) / (4 * trail_words64)));
+    const int blocks = (nworkers + wpb - 1) / wpb;
     long long want = (long long)B + 2LL * nworkers + 2LL * L0.split_target + 1024;
     if (want > (1LL << 26)) want = 1LL << 26;
     uint32_t cap = 4096;
@@ -699,6 +717,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     P.mode = mode;
     P.layout = layout;
     P.branching = L0.branching;
+    P.two_way = L0.two_way;
     P.q = (QCtl *)ctx->q.p;
     P.qseq = (uint32_t *)ctx->qseq.p;
     P.qdata = (uint32_t *)ctx->qdata.p;
@@ -707,6 +726,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     P.trail = (uint32_t *)ctx->trail.p;
     P.frame_words = frame_words;
     P.trail_words = trail_words;
+    P.max_frames = (int32_t)frames;
     P.nworkers = nworkers;
     P.donate = L0.donate ? 1 : 0;
     P.split_target = L0.split_target;
@@ -785,6 +805,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         r.ms = ms;
         r.kernel_ms = kms;
         r.traces = std::min<unsigned long long>(ntraces, P.trace_cap);
+        if (qh.stop_reason == 4) return fail(CUBICS_EDEVICE, "internal error: trail overflow");
         const bool stopped = qh.stop != 0;
         const int stop_verdict = qh.stop_reason == 3 ? CUBICS_CANCELLED : CUBICS_LIMIT;
         if (mode == CUBICS_MODE_FIRST) {

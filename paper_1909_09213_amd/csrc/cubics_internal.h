@@ -99,8 +99,8 @@ constexpr uint32_t SIG_DONE = 1u << 29;  // some instance's done flag is set
 constexpr uint32_t SIG_STOP = 1u << 30;  // the whole launch stops
 
 // Queue slot / trail frame header layout (uint32 words).
-constexpr int SLOT_HDR = 16;   // [0] inst [1] kind [2] x [3] depth [4..12) vals
-constexpr int FRAME_HDR = 32;  // [0] x [1] depth [2] flags [4..12) vals [16..21) features [24..26) node stamp
+constexpr int SLOT_HDR = 16;   // [0] inst [1] kind [2] x [3] depth [4..12) vals [12] side
+constexpr int FRAME_HDR = 32;  // [0] x [1] depth [2] flags [3] side [4..12) vals [16..21) features [24..26) node stamp
 
 // Learned policy (device).  Parameter vector theta (fp32 master copy):
 // W1[64][5] (hidden-major), b1[64], w2[64], b2 -> 449 values.
@@ -128,6 +128,7 @@ struct SearchParams {
     int32_t mode;
     int32_t layout;      // 1 LANE, 2 SEG
     int32_t branching;
+    int32_t two_way;     // 2-way branching: x = min D_x, then x != min D_x
     QCtl *q;
     uint32_t *qseq;
     uint32_t *qdata;
@@ -136,6 +137,7 @@ struct SearchParams {
     uint32_t *trail;
     uint32_t frame_words;
     uint32_t trail_words;  // per worker
+    int32_t max_frames;    // frames per worker trail (a push beyond stops the launch)
     int32_t nworkers;
     int32_t donate;
     long long split_target;

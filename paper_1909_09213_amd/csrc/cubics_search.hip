@@ -936,7 +936,7 @@ DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
 // parent snapshot snap, which is nw words in LDS or global memory).
 template <int WM>
 DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uint32_t (&vals)[WM],
-                    const uint32_t *snap, int nw, int lane) {
+                    const uint32_t *snap, int nw, int lane, int side = 0) {
     uint32_t cell = 0, pos = 0;
     int ok = 0;
     if (lane == 0) {
@@ -954,6 +954,7 @@ DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uin
         s[1] = (uint32_t)K_FRAME;
         s[2] = (uint32_t)x;
         s[3] = (uint32_t)depth;
+        s[12] = (uint32_t)side;
     }
     if (lane < WM) {
         uint32_t v = 0;
@@ -973,8 +974,21 @@ DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uin
 template <int WM>
 struct Frame {  // cached top-of-trail frame
     int x, depth;
+    int side;       // 2-way branching: 0 = next child x = min v, 1 = next child x in v
     uint32_t v[WM];
 };
+
+// A push beyond the trail's frames: stop the launch with an internal error
+// (the host sizes the trail for the deepest path, so this never fires).
+DEV bool trail_full(const SearchParams &P, int sp, int lane) {
+    if (sp < P.max_frames) return false;
+    if (lane == 0) {
+        P.q->stop_reason = 4;
+        st_rel_i(&P.q->stop, 1);
+        or_u(&P.q->signal, SIG_STOP);
+    }
+    return true;
+}
 
 template <int WM>
 DEV void frame_store_meta(uint32_t *f, const Frame<WM> &F, int lane) {
@@ -982,6 +996,7 @@ DEV void frame_store_meta(uint32_t *f, const Frame<WM> &F, int lane) {
         f[0] = (uint32_t)F.x;
         f[1] = (uint32_t)F.depth;
         f[2] = 0u;  // flags: bit 0 = part of the subtree left this worker
+        f[3] = (uint32_t)F.side;
     }
     if (lane < WM) {
         uint32_t v = 0;
@@ -995,6 +1010,7 @@ template <int WM>
 DEV void frame_load_meta(const uint32_t *f, Frame<WM> &F) {
     F.x = uni((int)f[0]);
     F.depth = uni((int)f[1]);
+    F.side = uni((int)f[3]);
 #pragma unroll
     for (int k = 0; k < WM; ++k) F.v[k] = uniu(f[4 + k]);
 }
@@ -1272,22 +1288,45 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             uint32_t dx[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) dx[k] = k < W ? uniu(L.dom[x * W + k]) : 0u;
+            int side0 = 0;
             if (split) {
-                // one FRAME task per value of x, each over this node's domains
+                // one FRAME task per child of x, each over this node's domains
+                // (d-way: one per value; 2-way: x = min, then x in the rest)
                 uint32_t rem[WM];
 #pragma unroll
                 for (int k = 0; k < WM; ++k) rem[k] = dx[k];
                 int pushed = 0;
+                if (P.two_way) {
+                    int lowk = 0;
 #pragma unroll
-                for (int k = 0; k < WM; ++k) {
-                    while (rem[k]) {
-                        const uint32_t lowb = rem[k] & (0u - rem[k]);
-                        uint32_t one[WM];
+                    for (int k = WM - 1; k >= 0; --k)
+                        if (rem[k]) lowk = k;
+                    uint32_t one[WM];
 #pragma unroll
-                        for (int q = 0; q < WM; ++q) one[q] = q == k ? lowb : 0u;
-                        if (!push_frame<WM>(P, b, x, depth, one, L.dom, nw, lane)) break;
-                        rem[k] &= ~lowb;
+                    for (int q = 0; q < WM; ++q) one[q] = q == lowk ? (rem[q] & (0u - rem[q])) : 0u;
+                    if (push_frame<WM>(P, b, x, depth, one, L.dom, nw, lane, 0)) {
+#pragma unroll
+                        for (int q = 0; q < WM; ++q) rem[q] &= ~one[q];
                         ++pushed;
+                        side0 = 1;
+                        if (push_frame<WM>(P, b, x, depth, rem, L.dom, nw, lane, 1)) {
+#pragma unroll
+                            for (int q = 0; q < WM; ++q) rem[q] = 0u;
+                            ++pushed;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < WM; ++k) {
+                        while (rem[k]) {
+                            const uint32_t lowb = rem[k] & (0u - rem[k]);
+                            uint32_t one[WM];
+#pragma unroll
+                            for (int q = 0; q < WM; ++q) one[q] = q == k ? lowb : 0u;
+                            if (!push_frame<WM>(P, b, x, depth, one, L.dom, nw, lane)) break;
+                            rem[k] &= ~lowb;
+                            ++pushed;
+                        }
                     }
                 }
                 if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
@@ -1302,6 +1341,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             }
             // push a trail frame: snapshot of this node, branch variable x
             {
+                if (trail_full(P, sp, lane)) return;
                 if (sp > 0 && lane < WM) {
                     // the outgoing top frame keeps its remaining values in HBM
                     uint32_t v = 0;
@@ -1310,6 +1350,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                         if (k == lane) v = F.v[k];
                     trail[(size_t)(sp - 1) * FW + 4 + lane] = v;
                 }
+                if (sp > 0 && lane == 63) trail[(size_t)(sp - 1) * FW + 3] = (uint32_t)F.side;
                 uint32_t *f = trail + (size_t)sp * FW;
                 for (int t = lane; t < nw; t += 64) f[FRAME_HDR + t] = L.dom[t];
                 if (cache_ok) {
@@ -1321,6 +1362,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 C.ubytes += 4ull * nw;
                 F.x = x;
                 F.depth = depth;
+                F.side = side0;
 #pragma unroll
                 for (int k = 0; k < WM; ++k) F.v[k] = dx[k];
                 frame_store_meta<WM>(f, F, lane);
@@ -1373,12 +1415,27 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             break;
         }
         {
-            int vi = -1;
+            // the child's domain of x: the smallest remaining value, or (2-way,
+            // second child) all the remaining values
+            uint32_t cv[WM];
+            if (P.two_way && F.side) {
 #pragma unroll
-            for (int k = WM - 1; k >= 0; --k)
-                if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
+                for (int k = 0; k < WM; ++k) {
+                    cv[k] = F.v[k];
+                    F.v[k] = 0u;
+                }
+            } else {
+                int vi = -1;
 #pragma unroll
-            for (int k = 0; k < WM; ++k) F.v[k] &= ~bit_in_word(vi, k);
+                for (int k = WM - 1; k >= 0; --k)
+                    if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
+#pragma unroll
+                for (int k = 0; k < WM; ++k) {
+                    cv[k] = bit_in_word(vi, k);
+                    F.v[k] &= ~cv[k];
+                }
+                if (P.two_way) F.side = 1;
+            }
             const uint32_t *f = trail + (size_t)(sp - 1) * FW;
             if (need_restore) {
                 if (snap_valid) {
@@ -1400,7 +1457,13 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 wsync();
             }
             need_restore = true;
-            if (lane < W) L.dom[F.x * W + lane] = bit_in_word(vi, lane);
+            if (lane < W) {
+                uint32_t w = 0u;
+#pragma unroll
+                for (int k = 0; k < WM; ++k)
+                    if (k == lane) w = cv[k];
+                L.dom[F.x * W + lane] = w;
+            }
             depth = F.depth + 1;
             dirty_one(L, n, F.x, lane);
         }
@@ -1488,7 +1551,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                     Frame<WM> D;
                     frame_load_meta<WM>(f, D);
                     if (tsel == sp - 1) D = F;
-                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, nw, lane)) {
+                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, nw, lane, D.side)) {
                         if (lane < WM) f[4 + lane] = 0u;
                         if (tracing)
                             for (int t = lane; t <= tsel; t += 64) trail[(size_t)t * FW + 2] = 1u;
@@ -1667,8 +1730,8 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
     uint32_t d = lane < n ? L.dom[lane] : 0u;
     uint32_t snapc = 0u, snapp = 0u;  // snapshots of frames sp - 1 and sp - 2
     bool snap_valid = false, snapp_valid = false;
-    int mx = 0, mdep = 0;  // frame `lane` (below the top): variable, depth
-    uint32_t mval = 0u;    // ... and its untried values
+    int mx = 0, mdep = 0, mside = 0;  // frame `lane` (below the top): variable, depth, side
+    uint32_t mval = 0u;               // ... and its untried values
 
     if (kind == K_ROOT) {
         for (int t = 0; t < I.n_unary; ++t) {
@@ -1711,30 +1774,51 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 if (prod < P.split_target) split = true;
             }
             uint32_t dx = (uint32_t)__builtin_amdgcn_readlane((int)d, x);
+            int side0 = 0;
             if (split) {
                 if (lane < n) L.dom[lane] = d;
                 wsync();
                 uint32_t rem = dx;
                 int pushed = 0;
-                while (rem) {
-                    const uint32_t lowb = rem & (0u - rem);
+                if (P.two_way) {
                     uint32_t one[WM];
 #pragma unroll
-                    for (int q = 0; q < WM; ++q) one[q] = q == 0 ? lowb : 0u;
-                    if (!push_frame<WM>(P, b, x, depth, one, L.dom, n, lane)) break;
-                    rem &= ~lowb;
-                    ++pushed;
+                    for (int q = 0; q < WM; ++q) one[q] = q == 0 ? (rem & (0u - rem)) : 0u;
+                    if (push_frame<WM>(P, b, x, depth, one, L.dom, n, lane, 0)) {
+                        rem &= ~one[0];
+                        ++pushed;
+                        side0 = 1;
+                        uint32_t rest[WM];
+#pragma unroll
+                        for (int q = 0; q < WM; ++q) rest[q] = q == 0 ? rem : 0u;
+                        if (push_frame<WM>(P, b, x, depth, rest, L.dom, n, lane, 1)) {
+                            rem = 0u;
+                            ++pushed;
+                        }
+                    }
+                } else {
+                    while (rem) {
+                        const uint32_t lowb = rem & (0u - rem);
+                        uint32_t one[WM];
+#pragma unroll
+                        for (int q = 0; q < WM; ++q) one[q] = q == 0 ? lowb : 0u;
+                        if (!push_frame<WM>(P, b, x, depth, one, L.dom, n, lane)) break;
+                        rem &= ~lowb;
+                        ++pushed;
+                    }
                 }
                 if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
                 if (!rem) goto next_child;
                 dx = rem;
             }
             {
+                if (trail_full(P, sp, lane)) return;
                 // the outgoing top frame's meta moves to its lane
                 if (sp > 0 && lane == sp - 1) {
                     mx = F.x;
                     mdep = F.depth;
                     mval = F.v[0];
+                    mside = F.side;
                 }
                 uint32_t *f = trail + (size_t)sp * FW;
                 if (lane < n) f[FRAME_HDR + lane] = d;
@@ -1745,6 +1829,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 snap_valid = true;
                 F.x = x;
                 F.depth = depth;
+                F.side = side0;
                 F.v[0] = dx;
 #pragma unroll
                 for (int k = 1; k < WM; ++k) F.v[k] = 0u;
@@ -1762,6 +1847,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 if (sp > 0) {
                     F.x = __builtin_amdgcn_readlane(mx, sp - 1);
                     F.depth = __builtin_amdgcn_readlane(mdep, sp - 1);
+                    F.side = __builtin_amdgcn_readlane(mside, sp - 1);
                     F.v[0] = (uint32_t)__builtin_amdgcn_readlane((int)mval, sp - 1);
                 }
             }
@@ -1783,8 +1869,17 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
             }
         }
         {
-            const int vi = __ffs(F.v[0]) - 1;
-            F.v[0] &= F.v[0] - 1;
+            // the child's domain of x: the smallest remaining value, or (2-way,
+            // second child) all the remaining values
+            uint32_t cv;
+            if (P.two_way && F.side) {
+                cv = F.v[0];
+                F.v[0] = 0u;
+            } else {
+                cv = F.v[0] & (0u - F.v[0]);
+                F.v[0] &= F.v[0] - 1;
+                if (P.two_way) F.side = 1;
+            }
             if (need_restore) {
                 if (!snap_valid) {
                     const uint32_t *f = trail + (size_t)(sp - 1) * FW;
@@ -1795,7 +1890,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 C.ubytes += 4ull * n;
             }
             need_restore = true;
-            if (lane == F.x) d = 1u << vi;
+            if (lane == F.x) d = cv;
             depth = F.depth + 1;
         }
         C.nodes += 1;
@@ -1872,11 +1967,12 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                     } else {
                         D.x = __builtin_amdgcn_readlane(mx, tsel);
                         D.depth = __builtin_amdgcn_readlane(mdep, tsel);
+                        D.side = __builtin_amdgcn_readlane(mside, tsel);
                         D.v[0] = (uint32_t)__builtin_amdgcn_readlane((int)mval, tsel);
 #pragma unroll
                         for (int k = 1; k < WM; ++k) D.v[k] = 0u;
                     }
-                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, n, lane)) {
+                    if (push_frame<WM>(P, b, D.x, D.depth, D.v, f + FRAME_HDR, n, lane, D.side)) {
                         if (tsel == sp - 1) F.v[0] = 0u;
                         else if (lane == tsel) mval = 0u;
                         C.steals += 1;
@@ -2012,6 +2108,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         Frame<WM> F0;
         F0.x = uni((int)s[2]);
         F0.depth = uni((int)s[3]);
+        F0.side = uni((int)s[12]);
 #pragma unroll
         for (int k = 0; k < WM; ++k) F0.v[k] = uniu(s[4 + k]);
         const InstDev I = TL ? IL : P.inst[b];

@@ -41,7 +41,7 @@ class Limits(ctypes.Structure):
         ("sol_capacity", ctypes.c_uint64), ("workers", ctypes.c_int32), ("donate", ctypes.c_int32),
         ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("explore_pm", ctypes.c_int32),
         ("trace_buf", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("two_way", ctypes.c_int32),
     ]
 
 
@@ -270,7 +270,7 @@ class Context:
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                 split_target, sol_capacity, workers, donate, policy, tables_in_lds=0,
-                trace=None, explore_pm=0, seed=0, use_graph=False):
+                trace=None, explore_pm=0, seed=0, use_graph=False, two_way=False):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -284,6 +284,7 @@ class Context:
         L.policy = policy.handle if policy is not None else None
         L.tables_in_lds = tables_in_lds
         L.use_graph = 1 if use_graph else 0
+        L.two_way = 1 if two_way else 0
         if trace is not None:
             L.trace_buf = trace.data_ptr()
             L.trace_capacity = trace.shape[0]
@@ -313,10 +314,10 @@ class Context:
               max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
               layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
               workers: int = 0, donate: bool = True, policy=None, tables_in_lds: int = 0,
-              use_graph: bool = False) -> Result:
+              use_graph: bool = False, two_way: bool = False) -> Result:
         L, buf = self._limits(prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                               split_target, sol_capacity, workers, donate, policy, tables_in_lds,
-                              use_graph=use_graph)
+                              use_graph=use_graph, two_way=two_way)
         r = _Result()
         _check(_lib.cubics_solve(prob.handle, mode, ctypes.byref(L), ctypes.byref(r)))
         return self._result(r, buf, prob.n)
@@ -325,7 +326,8 @@ class Context:
                     max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
-                    explore_pm: int = 0, seed: int = 0, use_graph: bool = False):
+                    explore_pm: int = 0, seed: int = 0, use_graph: bool = False,
+                    two_way: bool = False):
         """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
@@ -334,7 +336,7 @@ class Context:
         for b, p in enumerate(probs):
             L, buf = self._limits(p, mode, max_nodes, max_solutions, time_ms, branching, layout,
                                   split_target, sol_capacity, workers, donate, policy, 0,
-                                  trace if b == 0 else None, explore_pm, seed, use_graph)
+                                  trace if b == 0 else None, explore_pm, seed, use_graph, two_way)
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()

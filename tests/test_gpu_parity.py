@@ -218,3 +218,34 @@ def test_host_cancel_stops_a_running_solve(ctx, cb):
     # the next solve on the context starts with the flag cleared
     q = ctx.solve(ctx.load(cspgen.queens(8)), cb.MODE_COUNT)
     assert q.verdict == "SAT" and q.count == 92
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_two_way_branching(ctx, cb, layout):
+    """2-way branching (x = min D_x, then x != min D_x) against the oracle's:
+    counts, nodes, fails and solution sets, with donation, a split and one
+    worker."""
+    inst = cspgen.worked_example(0)
+    r = ctx.solve(ctx.load(inst), cb.MODE_ALL, layout=layout, sol_capacity=16, two_way=True)
+    assert (r.count, r.nodes, r.fails) == (11, 21, 0)
+    for idx in range(30):
+        inst = cspgen.mixed(idx + 7100, n=6, dmax=7, m=8)
+        _say("two-way mixed", idx, layout)
+        ref = oracle.solve(inst, oracle.MODE_ALL, sol_cap=20000, two_way=True)
+        r = ctx.solve(ctx.load(inst), cb.MODE_ALL, layout=layout, sol_capacity=max(ref.count, 1),
+                      two_way=True)
+        assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails), idx
+        assert _canon(r.solutions) == _canon(ref.solutions), idx
+    for idx in range(2):
+        inst = cspgen.rb(idx, n=20, d=8, dens_pm=300, tight_pm=390)
+        ref = oracle.solve(inst, oracle.MODE_COUNT, two_way=True)
+        p = ctx.load(inst)
+        # 64 workers donate large subtrees; 2-way paths run deeper than n + 1
+        # frames (a variable is branched on again after x != a)
+        for kw in ({}, {"split_target": 64}, {"workers": 1}, {"workers": 64}):
+            r = ctx.solve(p, cb.MODE_COUNT, layout=layout, two_way=True, **kw)
+            assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails), (idx, kw)
+    q = cspgen.queens(8)
+    ref = oracle.solve(q, oracle.MODE_COUNT, two_way=True)
+    r = ctx.solve(ctx.load(q), cb.MODE_COUNT, layout=layout, two_way=True, split_target=16)
+    assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails)
