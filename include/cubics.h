@@ -83,14 +83,17 @@ enum { CUBICS_BRANCH_FIRST_FAIL = 0, CUBICS_BRANCH_LEARNED = 1 };
    SEG   one lane per value of the revised variable (ballot-assembled), domains in LDS;
    VAR   one lane per variable, domains in registers (instances with at most 64
          variables of at most 32 values, binary constraints only, one constraint
-         per variable pair; other instances fall back to LANE);
-   AUTO  the autotuned choice for the instance's shape, else VAR when usable,
-         else SEG for domains wider than 24 values, else LANE. */
+         per variable pair, first-fail, and with 2-way branching only when
+         1 + sum_i (d_i - 1) <= 64; other cases fall back to LANE);
+   AUTO  the autotuned choice (layout and worker count) for the instance's
+         shape, else VAR for a single instance whose tables fit in LDS, else
+         SEG for domains wider than 24 values, else LANE. */
 enum { CUBICS_LAYOUT_AUTO = 0, CUBICS_LAYOUT_LANE = 1, CUBICS_LAYOUT_SEG = 2, CUBICS_LAYOUT_VAR = 3 };
 
 /* Supported range: 1 <= d_i <= 256 values per variable (at most 8 32-bit
    words per domain); n <= 1024 variables with n * ceil(dmax/32) <= 4096;
-   at most 65535 global (ALLDIFF / LINEAR_LE) constraints per instance. */
+   at most 65535 global (ALLDIFF / ALLDIFF_GAC / LINEAR_LE) constraints per
+   instance; ALLDIFF_GAC over at most 64 variables. */
 #define CUBICS_MAX_DOMAIN 256
 #define CUBICS_MAX_VARS 1024
 
