@@ -249,6 +249,44 @@ enum { CUBICS_AUTOTUNE_DIVS = 3 };
 int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
                     int64_t time_ms, int32_t *chosen, int32_t *chosen_div, double *rates);
 
+/* ------------------------------------------- large-neighbourhood search
+ * Minimise sum_i obj[i] * x_i (every obj[i] >= 0, at least one > 0) over the
+ * solutions of the CSP given as for cubics_load (the parallel large-
+ * neighbourhood search the paper names as future work, Sec. 3).  Round 0
+ * finds a first solution; each later round adds sum obj[i] x_i <= best - 1
+ * and solves `neighborhoods` copies in one persistent launch (find-first,
+ * max_nodes each): copy 0 frees every variable - if it is UNSAT the
+ * incumbent is optimal and the search stops - and the others fix each
+ * variable to its incumbent value except a random relax_pm per mille.  The
+ * best solution found is written to best (host, n int32 values).  Stops
+ * after `rounds` rounds (0 = until optimal or time_ms), when time_ms (0 =
+ * none) has passed, or on proof. */
+typedef struct {
+    int32_t neighborhoods;   /* copies per round, 1..65536 */
+    int32_t rounds;          /* 0 = no round limit */
+    int32_t relax_pm;        /* per mille of variables freed in copies 1.., 1..1000 */
+    uint32_t seed;           /* neighbourhood choice */
+    uint64_t max_nodes;      /* node budget of each copy; 0 = none */
+    int64_t time_ms;         /* overall wall budget; 0 = none */
+} cubics_lns_params;
+
+typedef struct {
+    int64_t objective;       /* of the best solution found (valid if found) */
+    int32_t found;           /* 1 if any solution was found */
+    int32_t optimal;         /* 1 if copy 0 proved that nothing better exists */
+    int32_t rounds;          /* rounds run */
+    int32_t improvements;    /* rounds that improved the incumbent (after round 0) */
+    uint64_t nodes;          /* search nodes over all copies and rounds */
+    double ms;               /* host wall time of the call */
+} cubics_lns_result;
+
+int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const int32_t *dsize,
+               const uint32_t *init_bits, int32_t m, const int32_t *type, const int32_t *arity,
+               const int64_t *var_off, const int32_t *vars, const int64_t *par_off,
+               const int64_t *params, const int64_t *tab_off, const uint32_t *tabs,
+               const int64_t *obj, const cubics_lns_params *lp, int32_t *best,
+               cubics_lns_result *res);
+
 /* -------------------------------------------------------- learned policy
  * The branching network (variable ordering, used when branching == LEARNED):
  * features f (5 per candidate variable) -> 64 ReLU units -> 1 output, the

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -85,6 +86,7 @@ struct cubics_ctx {
     int cu_count = 0;
     int wall_khz = 100000;
     DevBuf inst, ctl, q, qseq, qdata, trail, rootout, tracecnt;
+    DevBuf lnsdom, lnssol;  // large-neighbourhood search: initial domains, solutions
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     int32_t *cancel_host = nullptr;  // pinned, polled by the kernel
     struct Tuned {
@@ -103,6 +105,7 @@ struct cubics_prob {
     int n = 0, W = 1, dmax = 1;
     int n_units = 0, n_glob = 0;
     int64_t dsum = 0;  // sum over variables of (dsize - 1): bounds 2-way branchings on a path
+    int64_t last_lin_b = -1;  // gcoef index of the bound b of the last LINEAR_LE (or -1)
     bool has_table = false;
     bool has_gac = false;  // a GAC all-different (needs the larger LDS scratch)
     std::string bucket;
@@ -249,6 +252,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     std::vector<int32_t> deg(std::max(n, 1), 0);
     std::vector<double> tight_sum(std::max(n, 1), 0.0);
     bool has_table = false, has_gac = false;
+    int64_t last_lin_b = -1;
     for (int c = 0; c < m; ++c) {
         const int ty = type[c], k = arity[c];
         if (var_off[c + 1] - var_off[c] != k || k < 1)
@@ -331,6 +335,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
             g.k = k;
             g.scope_off = (int32_t)gscope.size();
             g.coef_off = (int32_t)gcoef.size();
+            if (ty == CUBICS_LINEAR_LE) last_lin_b = g.coef_off;
             if (ty != CUBICS_LINEAR_LE) {
                 // the scope's domains are compared in value space: base = the
                 // smallest lo; the span must fit the instance's domain words
@@ -471,6 +476,7 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     p->n_glob = (int)gdesc.size();
     p->has_table = has_table;
     p->has_gac = has_gac;
+    p->last_lin_b = last_lin_b;
     for (int i = 0; i < n; ++i) p->dsum += dsize[i] - 1;
     char *b8 = (char *)blob;
     InstDev &I = p->dev;
@@ -958,5 +964,152 @@ extern "C" int cubics_root(cubics_prob *p, int32_t layout, uint32_t *out_bits, i
     HIPCHK(hipMemcpyAsync(out_bits, dout, (size_t)p->n * p->W * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipMemcpyAsync(failed, dfail, 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
+    return CUBICS_OK;
+}
+
+// ------------------------------------------------ large-neighbourhood search
+//
+// Minimise sum_i c_i x_i (c_i >= 0) over the solutions of a CSP: the
+// instance is loaded once with one more constraint, sum c_i x_i <= UB, whose
+// bound is rewritten in the device copy every round.  A round solves B
+// neighbourhoods of the incumbent in one persistent launch (find-first, a
+// node budget each): neighbourhood 0 frees every variable (its UNSAT proves
+// the incumbent optimal), the others fix a random part of the variables to
+// the incumbent's values.  All neighbourhoods share the packed constraints;
+// only their initial domains differ.
+
+namespace {
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const int32_t *dsize,
+                          const uint32_t *init_bits, int32_t m, const int32_t *type, const int32_t *arity,
+                          const int64_t *var_off, const int32_t *vars, const int64_t *par_off,
+                          const int64_t *params, const int64_t *tab_off, const uint32_t *tabs,
+                          const int64_t *obj, const cubics_lns_params *lp, int32_t *best,
+                          cubics_lns_result *res) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!ctx || !obj || !lp || !best || !res) return fail(CUBICS_EINVAL, "NULL argument");
+    if (n < 1) return fail(CUBICS_EINVAL, "n must be >= 1");
+    if (lp->neighborhoods < 1 || lp->neighborhoods > 65536) return fail(CUBICS_EINVAL, "neighborhoods out of 1..65536");
+    if (lp->relax_pm < 1 || lp->relax_pm > 1000) return fail(CUBICS_EINVAL, "relax_pm out of 1..1000");
+    if (lp->rounds < 0 || lp->time_ms < 0) return fail(CUBICS_EINVAL, "negative rounds / time_ms");
+    memset(res, 0, sizeof *res);
+    // ---- the instance plus sum c_i x_i <= UB (variables with c_i > 0)
+    std::vector<int32_t> ob_vars;
+    std::vector<int64_t> ob_par(1, INT64_MAX / 4);
+    for (int i = 0; i < n; ++i) {
+        if (obj[i] < 0) return fail(CUBICS_EUNSUPPORTED, "objective coefficient %d is negative", i);
+        if (obj[i] > 0) {
+            ob_vars.push_back(i);
+            ob_par.push_back(obj[i]);
+        }
+    }
+    if (ob_vars.empty()) return fail(CUBICS_EINVAL, "the objective has no positive coefficient");
+    const int M = m + 1, k = (int)ob_vars.size();
+    std::vector<int32_t> ty(type, type + m), ar(arity, arity + m), vv(vars, vars + (m ? var_off[m] : 0));
+    std::vector<int64_t> vo(var_off, var_off + m + 1), po(par_off, par_off + m + 1), pa(params, params + (m ? par_off[m] : 0));
+    std::vector<int64_t> to(tab_off, tab_off + m + 1);
+    if (m == 0) { vo.assign(1, 0); po.assign(1, 0); to.assign(1, 0); }
+    ty.push_back(CUBICS_LINEAR_LE);
+    ar.push_back(k);
+    vv.insert(vv.end(), ob_vars.begin(), ob_vars.end());
+    vo.push_back((int64_t)vv.size());
+    pa.insert(pa.end(), ob_par.begin(), ob_par.end());
+    po.push_back((int64_t)pa.size());
+    to.push_back(to.back());
+    cubics_prob *base = nullptr;
+    int rc = cubics_load(ctx, n, lo, dsize, init_bits, M, ty.data(), ar.data(), vo.data(), vv.data(), po.data(),
+                         pa.data(), to.data(), tabs, &base);
+    if (rc) return rc;
+    std::unique_ptr<cubics_prob, void (*)(cubics_prob *)> guard(base, cubics_free);
+    const int W = base->W, B = lp->neighborhoods;
+    int64_t *d_bound = (int64_t *)base->dev.gcoef + base->last_lin_b;
+    std::vector<uint32_t> dom0((size_t)n * W);
+    HIPCHK(hipMemcpy(dom0.data(), base->dev.dom0, dom0.size() * 4, hipMemcpyDeviceToHost));
+    if ((rc = ctx->lnsdom.ensure(4ull * (size_t)B * n * W))) return rc;
+    if ((rc = ctx->lnssol.ensure(4ull * (size_t)B * n))) return rc;
+    // neighbourhoods: views of the base problem with their own initial domains
+    std::vector<cubics_prob> views(B, *base);
+    std::vector<cubics_prob *> vp(B);
+    for (int b = 0; b < B; ++b) {
+        views[b].blob = nullptr;  // not owned
+        views[b].dev.dom0 = (const uint32_t *)ctx->lnsdom.p + (size_t)b * n * W;
+        vp[b] = &views[b];
+    }
+    std::vector<cubics_limits> lim(B);
+    std::vector<cubics_result> out(B);
+    std::vector<uint32_t> hdom((size_t)B * n * W);
+    std::vector<int32_t> sols((size_t)B * n), cur(n);
+    uint64_t rng = 0x5DEECE66Dull ^ ((uint64_t)lp->seed << 17);
+    auto objective = [&](const int32_t *x) {
+        int64_t f = 0;
+        for (int i = 0; i < n; ++i) f += obj[i] * (int64_t)x[i];
+        return f;
+    };
+    auto elapsed_ms = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    int64_t incumbent = 0;
+    bool have = false;
+    for (int round = 0;; ++round) {
+        // bound: strictly better than the incumbent (none yet: unbounded)
+        const int64_t ub = have ? incumbent - 1 : INT64_MAX / 4;
+        HIPCHK(hipMemcpy(d_bound, &ub, sizeof ub, hipMemcpyHostToDevice));
+        const int nb = have ? B : 1;  // the first round looks for any solution
+        for (int b = 0; b < nb; ++b) {
+            uint32_t *d = hdom.data() + (size_t)b * n * W;
+            memcpy(d, dom0.data(), dom0.size() * 4);
+            if (b == 0) continue;  // neighbourhood 0: every variable free
+            for (int i = 0; i < n; ++i) {
+                if ((int)(splitmix(rng) % 1000ull) < lp->relax_pm) continue;  // freed
+                const int a = cur[i] - lo[i];
+                for (int w = 0; w < W; ++w) d[(size_t)i * W + w] = (w == a / 32) ? (1u << (a % 32)) : 0u;
+            }
+        }
+        HIPCHK(hipMemcpy(ctx->lnsdom.p, hdom.data(), 4ull * nb * n * W, hipMemcpyHostToDevice));
+        for (int b = 0; b < nb; ++b) {
+            memset(&lim[b], 0, sizeof(cubics_limits));
+            lim[b].max_nodes = lp->max_nodes;
+            lim[b].donate = 1;
+            lim[b].sol_buf = (int32_t *)ctx->lnssol.p + (size_t)b * n;
+            lim[b].sol_capacity = 1;
+        }
+        if (lp->time_ms > 0) lim[0].time_ms = std::max<int64_t>(1, lp->time_ms - (int64_t)elapsed_ms());
+        if ((rc = solve_impl(vp.data(), nb, CUBICS_MODE_FIRST, lim.data(), out.data()))) return rc;
+        HIPCHK(hipMemcpy(sols.data(), ctx->lnssol.p, 4ull * nb * n, hipMemcpyDeviceToHost));
+        res->rounds = round + 1;
+        int pick = -1;
+        int64_t fbest = 0;
+        for (int b = 0; b < nb; ++b) {
+            res->nodes += out[b].nodes;
+            if (out[b].verdict != CUBICS_SAT) continue;
+            const int64_t f = objective(sols.data() + (size_t)b * n);
+            if (pick < 0 || f < fbest) { pick = b; fbest = f; }
+        }
+        if (pick >= 0 && (!have || fbest < incumbent)) {
+            memcpy(cur.data(), sols.data() + (size_t)pick * n, sizeof(int32_t) * n);
+            if (have) res->improvements += 1;
+            incumbent = fbest;
+            have = true;
+        }
+        if (!have && out[0].verdict == CUBICS_UNSAT) break;        // the CSP has no solution
+        if (have && round > 0 && out[0].verdict == CUBICS_UNSAT && pick < 0) {
+            res->optimal = 1;  // no solution better than the incumbent exists
+            break;
+        }
+        if (!have && out[0].verdict != CUBICS_SAT) break;         // no solution within the budget
+        if (lp->rounds > 0 && round + 1 >= lp->rounds) break;
+        if (lp->time_ms > 0 && elapsed_ms() >= lp->time_ms) break;
+    }
+    res->found = have ? 1 : 0;
+    res->objective = incumbent;
+    if (have) memcpy(best, cur.data(), sizeof(int32_t) * n);
+    res->ms = elapsed_ms();
     return CUBICS_OK;
 }

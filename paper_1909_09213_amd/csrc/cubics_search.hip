@@ -1990,7 +1990,10 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
     const char *b0 = (const char *)g.blob;
     const char *t0 = (const char *)tab;
     I.lo = (const int32_t *)(t0 + ((const char *)g.lo - b0));
-    I.dom0 = (const uint32_t *)(t0 + ((const char *)g.dom0 - b0));
+    // initial domains may live outside the blob (the copies of a
+    // large-neighbourhood search share one blob with their own domains)
+    const char *d0 = (const char *)g.dom0;
+    I.dom0 = (d0 >= b0 && d0 < b0 + 4 * (size_t)g.blob_words) ? (const uint32_t *)(t0 + (d0 - b0)) : g.dom0;
     I.trig_off = (const int32_t *)(t0 + ((const char *)g.trig_off - b0));
     I.units = (const Unit *)(t0 + ((const char *)g.units - b0));
     I.rows = (const uint32_t *)(t0 + ((const char *)g.rows - b0));

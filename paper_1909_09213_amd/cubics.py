@@ -45,6 +45,18 @@ class Limits(ctypes.Structure):
     ]
 
 
+class LnsParams(ctypes.Structure):
+    _fields_ = [("neighborhoods", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("relax_pm", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("max_nodes", ctypes.c_uint64), ("time_ms", ctypes.c_int64)]
+
+
+class LnsResult(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_int64), ("found", ctypes.c_int32), ("optimal", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("improvements", ctypes.c_int32),
+                ("nodes", ctypes.c_uint64), ("ms", ctypes.c_double)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [
         ("verdict", ctypes.c_int32), ("truncated", ctypes.c_int32),
@@ -96,6 +108,9 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_cancel.argtypes = [vp]
     lib.cubics_cancel.restype = None
     lib.cubics_load.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.cubics_lns.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                               ctypes.POINTER(LnsParams), vp, ctypes.POINTER(LnsResult)]
+    lib.cubics_lns.restype = ctypes.c_int
     lib.cubics_free.argtypes = [vp]
     lib.cubics_free.restype = None
     lib.cubics_prob_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
@@ -199,8 +214,9 @@ class Context:
         _lib.cubics_cancel(self.handle)
 
     # ---------------------------------------------------------------- load
-    def load(self, inst) -> Problem:
-        keep = dict(
+    @staticmethod
+    def _arrays(inst):
+        return dict(
             lo=np.ascontiguousarray(inst.lo, dtype=np.int32),
             dsize=np.ascontiguousarray(inst.dsize, dtype=np.int32),
             type=np.ascontiguousarray(inst.type, dtype=np.int32),
@@ -212,6 +228,9 @@ class Context:
             tab_off=np.ascontiguousarray(inst.tab_off, dtype=np.int64),
             tabs=np.ascontiguousarray(inst.tabs, dtype=np.uint32),
         )
+
+    def load(self, inst) -> Problem:
+        keep = self._arrays(inst)
         init = None if inst.init is None else np.ascontiguousarray(inst.init, dtype=np.uint32)
         h = ctypes.c_void_p()
         _check(_lib.cubics_load(
@@ -220,6 +239,26 @@ class Context:
             _ptr(keep["par_off"]), _ptr(keep["params"]), _ptr(keep["tab_off"]), _ptr(keep["tabs"]),
             ctypes.byref(h)))
         return Problem(self, h, inst)
+
+    def lns(self, inst, obj, *, neighborhoods: int = 256, rounds: int = 0, relax_pm: int = 300,
+            max_nodes: int = 100_000, time_ms: int = 0, seed: int = 1) -> dict:
+        """cubics_lns: minimise sum obj[i] * x_i over the solutions of inst."""
+        keep = self._arrays(inst)
+        init = None if inst.init is None else np.ascontiguousarray(inst.init, dtype=np.uint32)
+        ob = np.ascontiguousarray(obj, dtype=np.int64)
+        if ob.shape != (inst.n,):
+            raise ValueError("obj must have one coefficient per variable")
+        best = np.zeros(max(inst.n, 1), dtype=np.int32)
+        lp = LnsParams(neighborhoods, rounds, relax_pm, seed, max_nodes, time_ms)
+        r = LnsResult()
+        _check(_lib.cubics_lns(
+            self.handle, inst.n, _ptr(keep["lo"]), _ptr(keep["dsize"]), _ptr(init), inst.m,
+            _ptr(keep["type"]), _ptr(keep["arity"]), _ptr(keep["var_off"]), _ptr(keep["vars"]),
+            _ptr(keep["par_off"]), _ptr(keep["params"]), _ptr(keep["tab_off"]), _ptr(keep["tabs"]),
+            _ptr(ob), ctypes.byref(lp), best.ctypes.data, ctypes.byref(r)))
+        return {"best": best[:inst.n].copy() if r.found else None, "objective": int(r.objective),
+                "found": bool(r.found), "optimal": bool(r.optimal), "rounds": int(r.rounds),
+                "improvements": int(r.improvements), "nodes": int(r.nodes), "ms": float(r.ms)}
 
     # ------------------------------------------------------------ autotune
     def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, rates: bool = False, **kw):

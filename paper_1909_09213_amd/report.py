@@ -11,6 +11,8 @@
                   split into 65,536 subproblems
   learned         traces -> GPU training -> learned vs first-fail node counts
                   and time-to-all on held-out seeds (same layout, same launch)
+  lns             large-neighbourhood search minimising the sum of the
+                  variables of an RB instance (n=60, d=12): objective per round
 
 Every count and verdict the library returns is checked where a closed value
 is known (queens); parity against the oracle is the tests' business.
@@ -87,6 +89,17 @@ def main():
         _emit({"config": "global_capped", "count": r.count, "verdict": r.verdict, "nodes": r.nodes,
                "fails": r.fails, "tasks": r.tasks, "kernel_ms": r.kernel_ms,
                "nodes_per_s": r.nodes / (r.kernel_ms * 1e-3)})
+
+    if "lns" not in skip:
+        inst = cspgen.rb(5, n=60, d=12, dens_pm=200, tight_pm=300)
+        obj = [1] * inst.n
+        trace = []
+        for rounds in (1, 2, 4, 8, 16):
+            r = ctx.lns(inst, obj, neighborhoods=1024, relax_pm=200, max_nodes=20000, rounds=rounds, seed=7)
+            trace.append({"rounds": r["rounds"], "objective": r["objective"], "ms": round(r["ms"], 1),
+                          "nodes": r["nodes"], "optimal": r["optimal"]})
+        _emit({"config": "lns", "instance": "RB n=60 d=12 density 0.2 tightness 0.3, minimise sum x",
+               "neighborhoods": 1024, "relax_pm": 200, "max_nodes_per_copy": 20000, "runs": trace})
 
     if "learned" not in skip:
         rep = learn.experiment(ctx, n_train=args.learned_train, n_eval=args.learned_eval,

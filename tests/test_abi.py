@@ -46,6 +46,9 @@ def test_null_arguments_are_rejected_without_gpu_work():
     assert lib.cubics_solve(None, 0, None, None) == -1
     lib.cubics_features.restype = ctypes.c_int
     assert lib.cubics_features(None, None, 0, None) == -1
+    lib.cubics_lns.restype = ctypes.c_int
+    assert lib.cubics_lns(None, 0, None, None, None, 0, None, None, None, None, None, None, None, None,
+                          None, None, None, None) == -1
     lib.cubics_autotune.restype = ctypes.c_int
     assert lib.cubics_autotune(None, 0, 0, None, ctypes.c_int64(1), None, None, None) == -1
     lib.cubics_free(None)
