@@ -647,7 +647,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     // ---- workers: fill the device with co-resident wavefronts.  A single
     // instance whose packed tables fit is staged in LDS once per workgroup;
     // the register-resident VAR path uses 8 workers per workgroup to share it.
-    const size_t LDS_WG_MAX = 64 * 1024;
+    const size_t LDS_WG_MAX = 64 * 1024 - 256;  // the kernel keeps a few static words
     const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
     bool var_all = G.wmax == 1;
     for (int b = 0; b < B && var_all; ++b) var_all = probs[b]->dev.var_ok != 0;

@@ -115,6 +115,18 @@ DEV void st_rlx(uint32_t *p, uint32_t v) {
 // device-scope fences: acquire invalidates, release writes back this XCD's L2
 DEV void fence_acq() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 DEV void fence_rel() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+// Queue slots move between XCDs through device-coherent (agent-scope)
+// accesses only, so handing one over needs no write-back of the producer's
+// whole L2 (an agent release) and no invalidation of the consumer's (an agent
+// acquire): the producer waits until its slot stores are acknowledged before
+// it publishes the slot's sequence word, and the consumer reads the slot only
+// after it has claimed that word.  With thousands of hand-overs per second in
+// a search's tail, the L2-wide fences stall every worker on the XCD.
+DEV void slot_stores_done() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps the compiler's order
+    __builtin_amdgcn_s_waitcnt(0);                          // vmcnt(0): stores acknowledged
+}
+DEV void slot_claimed() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup"); }
 DEV u64 add_u64(u64 *p, u64 v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -122,6 +134,14 @@ DEV bool cas_u32(uint32_t *p, uint32_t *expected, uint32_t desired) {
     return __hip_atomic_compare_exchange_strong(p, expected, desired, __ATOMIC_RELAXED,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// workgroup-scope words in LDS (the idle-poll token)
+DEV bool lds_take(uint32_t *p) {
+    uint32_t e = 0u;
+    return __hip_atomic_compare_exchange_strong(p, &e, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+DEV uint32_t lds_ld(uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+DEV void lds_st(uint32_t *p, uint32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 DEV bool cas_i(int32_t *p, int expected, int desired) {
     return __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_ACQ_REL,
                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -888,29 +908,11 @@ DEV int node_test(const InstDev &I, const Lds &L, int lane, int *bx) {
 // Called by lane 0 only.  Every poll uses relaxed loads, so idle workers never
 // invalidate caches; a successful pop or reserve is followed by one acquire
 // fence, and publishing is preceded by one release fence.
-DEV bool q_maybe_nonempty(const SearchParams &P) {
-    return ld_rlx(&P.q->tail) != ld_rlx(&P.q->head);
-}
-DEV bool q_pop(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
-    uint32_t pos = ld_rlx(&P.q->head);
-    for (;;) {
-        const uint32_t c = pos & P.qmask;
-        const uint32_t s = ld_rlx(&P.qseq[c]);
-        const int dif = (int)(s - (pos + 1u));
-        if (dif == 0) {
-            if (cas_u32(&P.q->head, &pos, pos + 1u)) {
-                fence_acq();
-                *cell = c;
-                *posout = pos;
-                return true;
-            }
-        } else if (dif < 0) {
-            return false;
-        } else {
-            pos = ld_rlx(&P.q->head);
-        }
-    }
-}
+// Consumers take tickets: an idle wave claims the next position with one
+// fetch-add on the head and waits on that position's own sequence word until
+// a producer publishes it.  Compare-and-swap pops made every polling wave
+// race for each new task, a storm of atomics on one word per hand-over that
+// capped hand-overs at a few 10^4 per second in a search's tail.
 DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
     uint32_t pos = ld_rlx(&P.q->tail);
     for (;;) {
@@ -919,7 +921,7 @@ DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
         const int dif = (int)(s - pos);
         if (dif == 0) {
             if (cas_u32(&P.q->tail, &pos, pos + 1u)) {
-                fence_acq();
+                slot_claimed();
                 *cell = c;
                 *posout = pos;
                 return true;
@@ -949,22 +951,20 @@ DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uin
     cell = uniu(cell);
     pos = uniu(pos);
     uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
-    if (lane == 0) {
-        s[0] = (uint32_t)inst;
-        s[1] = (uint32_t)K_FRAME;
-        s[2] = (uint32_t)x;
-        s[3] = (uint32_t)depth;
-        s[12] = (uint32_t)side;
-    }
-    if (lane < WM) {
-        uint32_t v = 0;
+    if (lane < SLOT_HDR) {  // header word `lane`
+        uint32_t h = 0u;
+        if (lane == 0) h = (uint32_t)inst;
+        if (lane == 1) h = (uint32_t)K_FRAME;
+        if (lane == 2) h = (uint32_t)x;
+        if (lane == 3) h = (uint32_t)depth;
+        if (lane == 12) h = (uint32_t)side;
 #pragma unroll
         for (int k = 0; k < WM; ++k)
-            if (k == lane) v = vals[k];
-        s[4 + lane] = v;
+            if (lane == 4 + k) h = vals[k];
+        st_rlx(s + lane, h);
     }
-    for (int t = lane; t < nw; t += 64) s[SLOT_HDR + t] = snap[t];
-    fence_rel();
+    for (int t = lane; t < nw; t += 64) st_rlx(s + SLOT_HDR + t, snap[t]);
+    slot_stores_done();
     if (lane == 0) st_rlx(&P.qseq[cell], pos + 1u);
     return true;
 }
@@ -1091,7 +1091,17 @@ DEV void flush(InstCtl *ctl, Counters &C, int lane) {
     C.rev = C.bytes = C.ubytes = 0;
 }
 
-constexpr int POLL = 128;  // nodes between checks of stop flags and donation requests
+// Nodes between checks of stop flags and donation requests.  Each check may
+// donate a frame; in the register layout, where a node costs a fraction of a
+// microsecond, checking every 128 nodes split a search's tail into so many
+// small tasks that it ran for longer than the rest of the search (RB n=40
+// d=16 slice x0=1 with 6144 workers: 19 s at 128, 7.5 s at 512, 3.6 s at
+// 2048; checking after 128 nodes and then at doubling intervals brought the
+// small tasks back: 19 s).  The LDS layouts keep 128: their many-instance and
+// small searches need the faster spreading (13-queens: 20 ms at 128, 66 ms at
+// 512).
+constexpr int POLL = 128;
+constexpr int POLL_VAR = 2048;
 
 
 // ------------------------------------------------------ branching policy
@@ -1491,14 +1501,15 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             since_poll = 0;
             // one shared word per poll; stop, done and queue words only when
             // it says so
-            int stop = 0, idle = 0;
-            u64 qlen = 0;
+            int stop = 0, want = 0;
             if (lane == 0) {
                 const uint32_t sig = ld_rlx(&P.q->signal);
                 stop = (sig & SIG_STOP) ? 1 : ((sig & SIG_DONE) ? ld_rlx_i(&ctl->done) : 0);
-                idle = (int)(sig & SIG_IDLE_MASK);
-                if (P.donate && idle > 0) qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
-                else idle = 0;
+                // donate while fewer tasks wait unclaimed than waves are idle
+                // (a negative difference: tickets waiting for a task)
+                const int idle = (int)(sig & SIG_IDLE_MASK);
+                if (P.donate && idle > 0)
+                    want = (int)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head)) < idle;
             }
             stop = uni(stop);
             if (stop) return;
@@ -1527,8 +1538,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 }
                 if (uni(st2)) return;
             }
-            idle = uni(idle);
-            if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
+            if (uni(want) && sp > 0) {
                 // donate the shallowest frame that still has untried values
                 int tsel = -1;
                 // (frames below the top keep their values in HBM; the top's are in F)
@@ -1913,19 +1923,20 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 open_x = bx;
             }
         }
-        if (++since_poll >= POLL) {
+        if (++since_poll >= POLL_VAR) {
             fold_var(C);
             since_poll = 0;
             // one shared word per poll; stop, done and queue words only when
             // it says so
-            int stop = 0, idle = 0;
-            u64 qlen = 0;
+            int stop = 0, want = 0;
             if (lane == 0) {
                 const uint32_t sig = ld_rlx(&P.q->signal);
                 stop = (sig & SIG_STOP) ? 1 : ((sig & SIG_DONE) ? ld_rlx_i(&ctl->done) : 0);
-                idle = (int)(sig & SIG_IDLE_MASK);
-                if (P.donate && idle > 0) qlen = (u64)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head));
-                else idle = 0;
+                // donate while fewer tasks wait unclaimed than waves are idle
+                // (a negative difference: tickets waiting for a task)
+                const int idle = (int)(sig & SIG_IDLE_MASK);
+                if (P.donate && idle > 0)
+                    want = (int)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head)) < idle;
             }
             if (uni(stop)) return;
             if (I.max_nodes) {
@@ -1939,8 +1950,8 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 }
             }
             // the clock and the host's cancel flag (a read over PCIe) every
-            // 16th poll
-            if ((P.time_ticks || P.cancel) && (++polls & 15) == 0) {
+            // 4th poll
+            if ((P.time_ticks || P.cancel) && (++polls & 3) == 0) {
                 int st2 = 0;
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
@@ -1953,8 +1964,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 }
                 if (uni(st2)) return;
             }
-            idle = uni(idle);
-            if (idle > 0 && (long long)uni64(qlen) < (long long)idle && sp > 0) {
+            if (uni(want) && sp > 0) {
                 // donate the shallowest frame that still has untried values
                 const u64 m = __ballot(lane < sp - 1 && mval != 0u);
                 int tsel = m ? __ffsll((long long)m) - 1 : -1;
@@ -2015,6 +2025,14 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC, bool VAR = false>
 __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
+    // idle_token: 1 while one idle wave of this workgroup polls the global
+    // queue; drained: set once that wave saw no task pending anywhere
+    __shared__ uint32_t idle_token, drained;
+    if (threadIdx.x == 0) {
+        idle_token = 0u;
+        drained = 0u;
+    }
+    __syncthreads();
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int wid = blockIdx.x * (blockDim.x >> 6) + wave;
@@ -2077,49 +2095,81 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     const long long t_start = (long long)wall_clock64();
     Counters C = {};
     bool idle = false;
-    // Idle workers back off exponentially (up to ~27 us between polls): with
-    // thousands of waves polling the same queue words, the polls themselves
-    // would otherwise saturate the memory-side atomics the busy workers need.
+    // Idle waves: only the one holding its workgroup's token takes a ticket
+    // and waits on its cell (backing off exponentially, up to ~27 us between
+    // polls); the others wait on the token in LDS.  A wave holding a ticket
+    // leaves when no task is pending anywhere (no task can appear again), and
+    // tells its workgroup through LDS.
     int backoff = 1;
+    int poller = 0;  // wave-uniform: this wave holds the token
+    int have_ticket = 0, polls = 0;
+    uint32_t ticket = 0;
     for (;;) {
         uint32_t cell = 0, pos = 0;
-        int got = 0;
-        if (lane == 0 && q_maybe_nonempty(P)) got = q_pop(P, &cell, &pos) ? 1 : 0;
-        got = uni(got);
-        if (!got) {
-            int pend = 0;
-            if (lane == 0) {
-                if (!idle) add_u(&P.q->signal, 1u);
-                pend = ld_rlx_i(&P.q->pending);
+        int got = 0, fin = 0;
+        if (!poller) {
+            int t = 0;
+            if (lane == 0) t = lds_take(&idle_token) ? 1 : 0;
+            poller = uni(t);
+            if (poller) backoff = 1;
+        }
+        if (poller) {
+            if (!have_ticket) {
+                if (lane == 0) ticket = add_u(&P.q->head, 1u);
+                ticket = uniu(ticket);
+                have_ticket = 1;
+                polls = 0;
             }
+            if (lane == 0) {
+                got = ld_rlx(&P.qseq[ticket & P.qmask]) == ticket + 1u;
+                if (!got && (++polls & 1) == 0 && ld_rlx_i(&P.q->pending) == 0) {
+                    fin = 1;
+                    lds_st(&drained, 1u);
+                }
+            }
+            got = uni(got);
+        } else if (lane == 0) {
+            fin = lds_ld(&drained) != 0u;
+        }
+        if (!got) {
+            if (lane == 0 && !idle) add_u(&P.q->signal, 1u);
             idle = true;
-            if (uni(pend) == 0) break;
-            for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(32);
-            backoff = backoff < 32 ? backoff * 2 : 32;
+            if (uni(fin)) break;
+            if (poller) {
+                for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(32);
+                backoff = backoff < 32 ? backoff * 2 : 32;
+            } else {
+                __builtin_amdgcn_s_sleep(16);
+            }
             continue;
         }
+        slot_claimed();
+        pos = ticket;
+        cell = ticket & P.qmask;
+        have_ticket = 0;
+        if (lane == 0) lds_st(&idle_token, 0u);  // hand the token on
+        poller = 0;
         backoff = 1;
         if (idle) {
             if (lane == 0) add_u(&P.q->signal, 0xFFFFFFFFu);  // idle - 1
             idle = false;
         }
-        cell = uniu(cell);
-        pos = uniu(pos);
-        const uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
-        const int b = uni((int)s[0]);
-        const int kind = uni((int)s[1]);
+        uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
+        const uint32_t hw = lane < SLOT_HDR ? ld_rlx(s + lane) : 0u;  // header word `lane`
+        const int b = __builtin_amdgcn_readlane((int)hw, 0);
+        const int kind = __builtin_amdgcn_readlane((int)hw, 1);
         Frame<WM> F0;
-        F0.x = uni((int)s[2]);
-        F0.depth = uni((int)s[3]);
-        F0.side = uni((int)s[12]);
+        F0.x = __builtin_amdgcn_readlane((int)hw, 2);
+        F0.depth = __builtin_amdgcn_readlane((int)hw, 3);
+        F0.side = __builtin_amdgcn_readlane((int)hw, 12);
 #pragma unroll
-        for (int k = 0; k < WM; ++k) F0.v[k] = uniu(s[4 + k]);
+        for (int k = 0; k < WM; ++k) F0.v[k] = (uint32_t)__builtin_amdgcn_readlane((int)hw, 4 + k);
         const InstDev I = TL ? IL : P.inst[b];
         const int nw = I.n * I.W;
         if (kind == K_ROOT) {
             for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
         } else {
-            for (int t = lane; t < nw; t += 64) L.dom[t] = s[SLOT_HDR + t];
+            for (int t = lane; t < nw; t += 64) L.dom[t] = ld_rlx(s + SLOT_HDR + t);
         }
         wsync();
         // the slot's words are in LDS now: hand the cell back to producers
