@@ -218,7 +218,12 @@ int cubics_root(cubics_prob *prob, int32_t layout, uint32_t *out_bits, int32_t *
    ascending order; LEARNED picks the variable by the policy network instead,
    which changes the order of the search but never its result.
    Hitting max_nodes / max_solutions / time_ms is a verdict (LIMIT), not an
-   error.  `limits` may be NULL (no limits, defaults). */
+   error.  Workers check them periodically: max_nodes every 128 nodes of a
+   worker, so a search may run up to 128 nodes per worker past it; a stop
+   (time_ms, cancel, another worker's find-first solution) is seen within
+   2048 nodes of a worker (the register layout without a node budget polls
+   that rarely: more frequent polls split its searches' tails too finely).
+   `limits` may be NULL (no limits, defaults). */
 int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits,
                  cubics_result *result);
 

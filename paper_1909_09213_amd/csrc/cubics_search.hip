@@ -1736,6 +1736,9 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
     bool have_open = false, need_restore = false;
     int depth = F0.depth;
     int since_poll = 0, polls = 0;
+    // a node budget is checked at every poll: keep it as fine as in the LDS
+    // layouts when there is one
+    const int poll_iv = I.max_nodes ? POLL : POLL_VAR;
     int open_x = 0;
     uint32_t d = lane < n ? L.dom[lane] : 0u;
     uint32_t snapc = 0u, snapp = 0u;  // snapshots of frames sp - 1 and sp - 2
@@ -1923,7 +1926,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 open_x = bx;
             }
         }
-        if (++since_poll >= POLL_VAR) {
+        if (++since_poll >= poll_iv) {
             fold_var(C);
             since_poll = 0;
             // one shared word per poll; stop, done and queue words only when
@@ -1950,8 +1953,8 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 }
             }
             // the clock and the host's cancel flag (a read over PCIe) every
-            // 4th poll
-            if ((P.time_ticks || P.cancel) && (++polls & 3) == 0) {
+            // 2048 nodes
+            if ((P.time_ticks || P.cancel) && (++polls & (poll_iv == POLL ? 15 : 0)) == 0) {
                 int st2 = 0;
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
