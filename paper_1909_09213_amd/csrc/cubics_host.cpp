@@ -285,11 +285,18 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                 if (ntab != (int64_t)di * Wj || !tab)
                     return fail(CUBICS_EINVAL, "constraint %d: TABLE2 needs %d x %d words", c, di, Wj);
                 has_table = true;
-                // rows indexed by the value of i (bits over j) and by the value of j (bits over i)
-                const int32_t off_ij = (int32_t)rows.size();
-                rows.resize(rows.size() + (size_t)di * W, 0u);
-                const int32_t off_ji = (int32_t)rows.size();
-                rows.resize(rows.size() + (size_t)dj * W, 0u);
+                // rows indexed by the value of i (bits over j) and by the value
+                // of j (bits over i).  Blocks of an even size get one word of
+                // padding: the lanes revising different constraints read row
+                // `a` of their own blocks at once, and blocks at a stride of
+                // 16 words would put them all in two of the 32 LDS banks.
+                const auto block = [&rows](size_t words) {
+                    const int32_t off = (int32_t)rows.size();
+                    rows.resize(rows.size() + words + (words % 2 == 0 ? 1 : 0), 0u);
+                    return off;
+                };
+                const int32_t off_ij = block((size_t)di * W);
+                const int32_t off_ji = block((size_t)dj * W);
                 int64_t allowed = 0;
                 for (int a = 0; a < di; ++a)
                     for (int b = 0; b < dj; ++b)
