@@ -116,8 +116,8 @@ def main():
                     help="run a 256 MiB device-to-device copy first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (single-GPU solver; "
-              "multi-GPU sharding is a design note, not implemented)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus must be 1 (sharding a "
+              "search over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.steps + args.warmup > 16:
         print("bench.py: need 1 <= steps and steps + warmup <= 16 (the instance has 16 slices)",

@@ -286,13 +286,16 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                     return fail(CUBICS_EINVAL, "constraint %d: TABLE2 needs %d x %d words", c, di, Wj);
                 has_table = true;
                 // rows indexed by the value of i (bits over j) and by the value
-                // of j (bits over i).  Blocks of an even size get one word of
-                // padding: the lanes revising different constraints read row
+                // of j (bits over i).  Every block is preceded by a zero word
+                // (row -1: the register layout's support union reads it for
+                // the positions past its last value) and blocks sit at an odd
+                // stride: the lanes revising different constraints read row
                 // `a` of their own blocks at once, and blocks at a stride of
                 // 16 words would put them all in two of the 32 LDS banks.
                 const auto block = [&rows](size_t words) {
+                    rows.push_back(0u);
                     const int32_t off = (int32_t)rows.size();
-                    rows.resize(rows.size() + words + (words % 2 == 0 ? 1 : 0), 0u);
+                    rows.resize(rows.size() + words + ((words + 1) % 2 == 0 ? 1 : 0), 0u);
                     return off;
                 };
                 const int32_t off_ij = block((size_t)di * W);

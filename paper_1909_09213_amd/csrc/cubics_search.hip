@@ -1596,20 +1596,20 @@ DEV int pair_qk(uint32_t e) { return (int)((e >> 15) & 0x1FFFu); }
 DEV int pair_qdl(uint32_t e) { return (int)(e << 17) >> 17; }
 
 // Support union of the rows of the source values in dj (uniform across the
-// wave): lowest and highest remaining bits, up to four row loads in flight,
-// with every bit operation on the scalar unit.
+// wave), four values per step with four row loads in flight.  s_ff1 finds the
+// lowest remaining value and s_bitset0 clears it: two scalar instructions per
+// value, where the scalar unit is what bounds this layout.  Past the last value
+// s_ff1 gives -1 (and s_bitset0 of bit 31 leaves an empty set empty); row -1
+// is the zero word the packer puts before every row block.
 DEV uint32_t table_union(const uint32_t *rows, uint32_t dj) {
     uint32_t acc = 0u, bits = dj;
     while (bits) {
-        const int a = __builtin_ctz(bits), b = 31 - __builtin_clz(bits);
-        bits &= ~((1u << a) | (1u << b));
-        if (bits) {
-            const int c = __builtin_ctz(bits), e = 31 - __builtin_clz(bits);
-            bits &= ~((1u << c) | (1u << e));
-            acc |= rows[a] | rows[b] | rows[c] | rows[e];
-        } else {
-            acc |= rows[a] | rows[b];
-        }
+        int a, b, c, e;
+        asm("s_ff1_i32_b32 %0, %1\n\ts_bitset0_b32 %1, %0" : "=&s"(a), "+s"(bits));
+        asm("s_ff1_i32_b32 %0, %1\n\ts_bitset0_b32 %1, %0" : "=&s"(b), "+s"(bits));
+        asm("s_ff1_i32_b32 %0, %1\n\ts_bitset0_b32 %1, %0" : "=&s"(c), "+s"(bits));
+        asm("s_ff1_i32_b32 %0, %1\n\ts_bitset0_b32 %1, %0" : "=&s"(e), "+s"(bits));
+        acc |= rows[a] | rows[b] | rows[c] | rows[e];
     }
     return acc;
 }
