@@ -34,3 +34,15 @@ def test_generators_hold_no_solver():
     code = re.sub(r"/\*.*?\*/", "", text, flags=re.S)  # comments may name the method
     for word in ("propagat", "revise", "backtrack", "fixpoint"):
         assert word not in code.lower()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: the refusal happens before anything touches a device
+    import subprocess
+    import sys
+    for extra, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + extra,
+                           capture_output=True, text=True, timeout=120,
+                           env=dict(os.environ, **env), cwd=ROOT)
+        assert r.returncode == 2, (extra, env, r.returncode, r.stderr[-300:])
+        assert "one GPU" in r.stderr and r.stdout == ""
