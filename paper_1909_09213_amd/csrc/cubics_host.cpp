@@ -244,7 +244,10 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
 
     // ---- constraints
     std::vector<Unit> units;
-    std::vector<uint32_t> rows;
+    // rows start with an all-ones block of 32 words: in the register layout
+    // a lane with no constraint to the revised source (pair entry 0, row
+    // offset 0) takes the support union of this block and keeps its domain
+    std::vector<uint32_t> rows(32, 0xFFFFFFFFu);
     std::vector<GDesc> gdesc;
     std::vector<int32_t> gscope;
     std::vector<int64_t> gcoef;

@@ -1659,11 +1659,17 @@ DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, in
             const uint32_t en = I.pairs[jn * 64 + lane];
             const uint32_t dj = (uint32_t)__builtin_amdgcn_readlane((int)d, j);
             uint32_t nd = d;
-            if (e != 0u) {
-                if (TYPES == 1) {
-                    nd = d & table_union(I.rows + pair_param(e), dj);
-                    C.vpop += __popc(d);
-                } else if (TYPES == 2) {
+            if (TYPES == 1) {
+                // every lane revises, without a branch on the lanes: a lane
+                // with no constraint to j (e == 0) reads the all-ones rows at
+                // offset 0 and keeps its domain
+                nd = d & table_union(I.rows + pair_param(e), dj);
+                const uint32_t real = e != 0u ? 1u : 0u;
+                C.vpop += real * (uint32_t)__popc(d);
+                C.vrev += real;
+                C.vchg += nd != d ? 1u : 0u;
+            } else if (e != 0u) {
+                if (TYPES == 2) {
                     if (__popc(dj) <= 3) {
                         const int kq = pair_qk(e);
                         const int dl = pair_qdl(e);
