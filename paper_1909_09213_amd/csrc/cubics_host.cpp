@@ -85,6 +85,7 @@ struct cubics_ctx {
     hipStream_t stream = nullptr;
     int cu_count = 0;
     int wall_khz = 100000;
+    int lds_max = 64 * 1024;  // LDS bytes one workgroup may allocate (160 KiB on gfx950)
     DevBuf inst, ctl, q, qseq, qdata, trail, rootout, tracecnt;
     DevBuf lnsdom, lnssol;  // large-neighbourhood search: initial domains, solutions
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -131,6 +132,7 @@ extern "C" int cubics_create(int32_t device, void *hip_stream, cubics_ctx **out)
         return fail(CUBICS_EDEVICE, "hipGetDeviceProperties failed");
     }
     c->cu_count = prop.multiProcessorCount;
+    if (prop.sharedMemPerBlock >= 64 * 1024) c->lds_max = (int)prop.sharedMemPerBlock;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
         c->wall_khz = khz;
@@ -246,7 +248,11 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     std::vector<Unit> units;
     // rows start with an all-ones block of 32 words: in the register layout
     // a lane with no constraint to the revised source (pair entry 0, row
-    // offset 0) takes the support union of this block and keeps its domain
+    // offset 0) takes the support union of this block and keeps its domain.
+    // Row offsets count from that block; the blob holds ROW_PRE zero words
+    // before it, so that row -1 of every block, the all-ones one included,
+    // lies inside the rows section.
+    constexpr int ROW_PRE = 8;
     std::vector<uint32_t> rows(32, 0xFFFFFFFFu);
     std::vector<GDesc> gdesc;
     std::vector<int32_t> gscope;
@@ -289,16 +295,16 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                     return fail(CUBICS_EINVAL, "constraint %d: TABLE2 needs %d x %d words", c, di, Wj);
                 has_table = true;
                 // rows indexed by the value of i (bits over j) and by the value
-                // of j (bits over i).  Every block is preceded by a zero word
-                // (row -1: the register layout's support union reads it for
-                // the positions past its last value) and blocks sit at an odd
-                // stride: the lanes revising different constraints read row
-                // `a` of their own blocks at once, and blocks at a stride of
-                // 16 words would put them all in two of the 32 LDS banks.
-                const auto block = [&rows](size_t words) {
-                    rows.push_back(0u);
+                // of j (bits over i).  Every block is preceded by W zero words
+                // (row -1: the revisions read it for the slots past their last
+                // value) and blocks sit at an odd stride: the lanes revising
+                // different constraints read row `a` of their own blocks at
+                // once, and blocks at a stride of 16 words would put them all
+                // in two of the 32 LDS banks.
+                const auto block = [&rows, W](size_t words) {
+                    rows.resize(rows.size() + W, 0u);
                     const int32_t off = (int32_t)rows.size();
-                    rows.resize(rows.size() + words + ((words + 1) % 2 == 0 ? 1 : 0), 0u);
+                    rows.resize(rows.size() + words + ((W + words) % 2 == 0 ? 1 : 0), 0u);
                     return off;
                 };
                 const int32_t off_ij = block((size_t)di * W);
@@ -453,8 +459,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
     const size_t o_dom0 = pk.add(dom0.data(), dom0.size() * 4);
     const size_t o_trig = pk.add(trig_off.data(), trig_off.size() * 4);
     const size_t o_units = pk.add(sorted.data(), std::max<size_t>(sorted.size(), 1) * sizeof(Unit));
-    if (rows.empty()) rows.push_back(0);
-    const size_t o_rows = pk.add(rows.data(), rows.size() * 4);
+    rows.insert(rows.begin(), ROW_PRE, 0u);
+    const size_t o_rows = pk.add(rows.data(), rows.size() * 4) + 4 * ROW_PRE;
     const size_t o_gto = pk.add(gtrig_off.data(), gtrig_off.size() * 4);
     const size_t o_gt = pk.add(gtrig.data(), gtrig.size() * 4);
     const size_t o_gd = pk.add(gdesc.data(), std::max<size_t>(gdesc.size(), 1) * sizeof(GDesc));
@@ -660,7 +666,7 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     // ---- workers: fill the device with co-resident wavefronts.  A single
     // instance whose packed tables fit is staged in LDS once per workgroup;
     // the register-resident VAR path uses 8 workers per workgroup to share it.
-    const size_t LDS_WG_MAX = 64 * 1024 - 256;  // the kernel keeps a few static words
+    const size_t LDS_WG_MAX = (size_t)ctx->lds_max - 256;  // the kernel keeps a few static words
     const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
     bool var_all = G.wmax == 1;
     for (int b = 0; b < B && var_all; ++b) var_all = probs[b]->dev.var_ok != 0;
@@ -1044,7 +1050,9 @@ extern "C" int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const i
     const int W = base->W, B = lp->neighborhoods;
     int64_t *d_bound = (int64_t *)base->dev.gcoef + base->last_lin_b;
     std::vector<uint32_t> dom0((size_t)n * W);
-    HIPCHK(hipMemcpy(dom0.data(), base->dev.dom0, dom0.size() * 4, hipMemcpyDeviceToHost));
+    hipStream_t st = ctx->stream;  // every copy runs on the context's stream
+    HIPCHK(hipMemcpyAsync(dom0.data(), base->dev.dom0, dom0.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
     if ((rc = ctx->lnsdom.ensure(4ull * (size_t)B * n * W))) return rc;
     if ((rc = ctx->lnssol.ensure(4ull * (size_t)B * n))) return rc;
     // neighbourhoods: views of the base problem with their own initial domains
@@ -1073,7 +1081,7 @@ extern "C" int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const i
     for (int round = 0;; ++round) {
         // bound: strictly better than the incumbent (none yet: unbounded)
         const int64_t ub = have ? incumbent - 1 : INT64_MAX / 4;
-        HIPCHK(hipMemcpy(d_bound, &ub, sizeof ub, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(d_bound, &ub, sizeof ub, hipMemcpyHostToDevice, st));
         const int nb = have ? B : 1;  // the first round looks for any solution
         for (int b = 0; b < nb; ++b) {
             uint32_t *d = hdom.data() + (size_t)b * n * W;
@@ -1085,7 +1093,9 @@ extern "C" int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const i
                 for (int w = 0; w < W; ++w) d[(size_t)i * W + w] = (w == a / 32) ? (1u << (a % 32)) : 0u;
             }
         }
-        HIPCHK(hipMemcpy(ctx->lnsdom.p, hdom.data(), 4ull * nb * n * W, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(ctx->lnsdom.p, hdom.data(), 4ull * nb * n * W, hipMemcpyHostToDevice, st));
+        // the host buffers are reused next round: wait for the copies
+        HIPCHK(hipStreamSynchronize(st));
         for (int b = 0; b < nb; ++b) {
             memset(&lim[b], 0, sizeof(cubics_limits));
             lim[b].max_nodes = lp->max_nodes;
@@ -1095,7 +1105,8 @@ extern "C" int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const i
         }
         if (lp->time_ms > 0) lim[0].time_ms = std::max<int64_t>(1, lp->time_ms - (int64_t)elapsed_ms());
         if ((rc = solve_impl(vp.data(), nb, CUBICS_MODE_FIRST, lim.data(), out.data()))) return rc;
-        HIPCHK(hipMemcpy(sols.data(), ctx->lnssol.p, 4ull * nb * n, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpyAsync(sols.data(), ctx->lnssol.p, 4ull * nb * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
         res->rounds = round + 1;
         int pick = -1;
         int64_t fbest = 0;

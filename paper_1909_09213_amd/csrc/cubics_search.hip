@@ -197,41 +197,101 @@ struct Counters {
     u64 stamp;                              // nodes of this worker, never reset
     u64 ubytes;                             // wave-uniform bytes (trail copies)
     // VAR layout, per lane, folded into rev / bytes at every poll and flush:
-    // revisions, revisions that changed the target, and the target popcounts
-    // of table revisions (bytes = 8 rev + 4 chg + 4 pop for one-word domains)
+    // revisions, revisions that changed the target, and the support rows that
+    // table revisions read, one per source value (bytes = 8 rev + 4 chg +
+    // 4 rows for one-word domains)
     uint32_t vrev, vchg, vpop;
 };
 
 // ------------------------------------------------- binary unit revisions
 
-// LANE layout: full new target words for one unit.
+// Rows fetched together by one lane of a LANE table revision: the lane
+// gathers up to RB live values, then issues all their row loads before it
+// uses any, so a revision waits on ceil(|D| / RB) memory round trips instead
+// of |D|.  A missing value reads row -1, the W zero words the packer puts
+// before every row block.
+constexpr int RB = 8;
+
+template <int WM>
+DEV void next_values(uint32_t &bits, int w, int (&ix)[RB]) {
+#pragma unroll
+    for (int q = 0; q < RB; ++q) {
+        ix[q] = bits ? 32 * w + __ffs(bits) - 1 : -1;
+        bits &= bits - 1u;
+    }
+}
+
+// LANE layout: full new target words for one unit.  A table revision reads
+// min(|D_src|, |D_tgt|) rows: the union of the source values' rows (bits over
+// the target) when the source is the smaller domain, else one row per live
+// target value (bits over the source), tested against the source domain.
+// *rows_read receives that count (the algorithmic row traffic).
 template <int WM>
 DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
-                     const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W) {
+                     const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W, int *rows_read) {
     const int ty = u.tt >> 24;
 #pragma unroll
     for (int k = 0; k < WM; ++k) nw[k] = dt[k];
+    *rows_read = 0;
     if (ty == U_TABLE) {
-        // union of the rows of the source values (bits over the target)
-        uint32_t acc[WM];
+        const int ps = pop_w(ds, W), pt = pop_w(dt, W);
+        if (ps <= pt) {
+            *rows_read = ps;
+            uint32_t acc[WM];
 #pragma unroll
-        for (int k = 0; k < WM; ++k) acc[k] = 0u;
-        const uint32_t *rows = I.rows + u.p1;
+            for (int k = 0; k < WM; ++k) acc[k] = 0u;
+            const uint32_t *rows = I.rows + u.p1;
 #pragma unroll
-        for (int w = 0; w < WM; ++w) {
-            if (w >= W) break;
-            uint32_t bits = ds[w];
-            while (bits) {
-                int b = 32 * w + __ffs(bits) - 1;
-                bits &= bits - 1;
-                const uint32_t *r = rows + (size_t)b * W;
+            for (int w = 0; w < WM; ++w) {
+                if (w >= W) break;
+                uint32_t bits = ds[w];
+                while (bits) {
+                    int ix[RB];
+                    next_values<WM>(bits, w, ix);
+                    uint32_t r[RB][WM];
 #pragma unroll
-                for (int k = 0; k < WM; ++k)
-                    if (k < W) acc[k] |= r[k];
+                    for (int q = 0; q < RB; ++q)
+#pragma unroll
+                        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? rows[(ptrdiff_t)ix[q] * W + k] : 0u;
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+#pragma unroll
+                        for (int k = 0; k < WM; ++k) acc[k] |= r[q][k];
+                }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
+            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
+        } else {
+            *rows_read = pt;
+            uint32_t keep[WM];
+#pragma unroll
+            for (int k = 0; k < WM; ++k) keep[k] = 0u;
+            const uint32_t *rows = I.rows + u.p0;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                if (w >= W) break;
+                uint32_t bits = dt[w];
+                while (bits) {
+                    int ix[RB];
+                    next_values<WM>(bits, w, ix);
+                    uint32_t r[RB][WM];
+#pragma unroll
+                    for (int q = 0; q < RB; ++q)
+#pragma unroll
+                        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? rows[(ptrdiff_t)ix[q] * W + k] : 0u;
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) {
+                        uint32_t hit = 0u;
+#pragma unroll
+                        for (int k = 0; k < WM; ++k) hit |= r[q][k] & ds[k];
+                        // ix = -1 reads a zero row: never supported
+                        if (hit) keep[w] |= 1u << (ix[q] & 31);
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < WM; ++k) nw[k] = keep[k];
+        }
     } else if (ty == U_NEQ) {
         if (pop_w(ds, W) == 1) {
             int a = low_w(ds, W) + u.p0;
@@ -300,12 +360,11 @@ DEV bool supported_seg(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM]
     }
 }
 
-// algorithmic bytes of one binary revision: both domains, the support rows of
-// the target's live values for a table, and the target written back if changed
-DEV u64 rev_bytes(int ty, int W, int pop_t, bool changed) {
-    u64 b = 8ull * W + (changed ? 4ull * W : 0ull);
-    if (ty == U_TABLE) b += 4ull * (u64)pop_t * (u64)W;
-    return b;
+// algorithmic bytes of one binary revision: both domains, the support rows
+// the revision reads for a table (rows of W words), and the target written
+// back if changed
+DEV u64 rev_bytes(int W, int rows, bool changed) {
+    return 8ull * W + (changed ? 4ull * W : 0ull) + 4ull * (u64)rows * (u64)W;
 }
 
 // LDS view of one worker.
@@ -333,11 +392,12 @@ DEV bool chunk_lane(const InstDev &I, const Lds &L, u64 *nxt, int my_u, Counters
             ds[k] = k < W ? L.dom[u.src * W + k] : 0u;
             dt[k] = k < W ? L.dom[tgt * W + k] : 0u;
         }
-        revise_lane<WM>(I, u, ds, dt, nw, W);
+        int rows_read = 0;
+        revise_lane<WM>(I, u, ds, dt, nw, W, &rows_read);
 #pragma unroll
         for (int k = 0; k < WM; ++k) changed |= (k < W) && nw[k] != dt[k];
         C.rev += 1;
-        C.bytes += rev_bytes(u.tt >> 24, W, pop_w(dt, W), changed);
+        C.bytes += rev_bytes(W, rows_read, changed);
         if (changed) {
 #pragma unroll
             for (int k = 0; k < WM; ++k)
@@ -391,7 +451,8 @@ DEV bool chunk_seg(const InstDev &I, const Lds &L, u64 *nxt, int my_u, int sh, C
 #pragma unroll
         for (int k = 0; k < WM; ++k) changed |= (k < W) && nw[k] != dt[k];
         C.rev += 1;
-        C.bytes += rev_bytes(u.tt >> 24, W, pop_w(dt, W), changed);
+        // one support row per live target value (each lane reads its own)
+        C.bytes += rev_bytes(W, (u.tt >> 24) == U_TABLE ? pop_w(dt, W) : 0, changed);
         if (changed) {
 #pragma unroll
             for (int k = 0; k < WM; ++k)
@@ -1665,7 +1726,8 @@ DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, in
                 // offset 0 and keeps its domain
                 nd = d & table_union(I.rows + pair_param(e), dj);
                 const uint32_t real = e != 0u ? 1u : 0u;
-                C.vpop += real * (uint32_t)__popc(d);
+                // the revision reads one row per value of the source
+                C.vpop += real * (uint32_t)__popc(dj);
                 C.vrev += real;
                 C.vchg += nd != d ? 1u : 0u;
             } else if (e != 0u) {
@@ -1683,7 +1745,7 @@ DEV bool propagate_var_t(const InstDev &I, uint32_t &d, u64 cur, Counters &C, in
                     }
                 } else {
                     nd = revise_var_generic(I, e, d, dj);
-                    if (pair_type(e) == U_TABLE) C.vpop += __popc(d);
+                    if (pair_type(e) == U_TABLE) C.vpop += __popc(dj);
                 }
                 C.vrev += 1u;
                 C.vchg += nd != d ? 1u : 0u;
@@ -2364,6 +2426,11 @@ int search_variant(int feat, bool glob, bool seg, bool var) {
 hipError_t launch_search(int wmax, const SearchParams &P, int blocks, int wpb, size_t lds, bool tl, int variant,
                          hipStream_t st) {
     const void *fn = search_fn_any(wmax, tl, variant);
+    if (lds > 64 * 1024) {
+        // beyond 64 KiB of dynamic LDS a kernel must opt in (gfx950: 160 KiB)
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     void *args[] = {(void *)&P};
     return hipLaunchKernel(fn, dim3(blocks), dim3(64 * wpb), args, lds, st);
 }

@@ -309,7 +309,8 @@ class Context:
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                 split_target, sol_capacity, workers, donate, policy, tables_in_lds=0,
-                trace=None, explore_pm=0, seed=0, use_graph=False, two_way=False):
+                trace=None, explore_pm=0, seed=0, use_graph=False, two_way=False,
+                no_buffer=False):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -330,7 +331,7 @@ class Context:
             L.explore_pm = explore_pm
             L.seed = seed
         buf = None
-        if mode == MODE_FIRST and sol_capacity == 0:
+        if mode == MODE_FIRST and sol_capacity == 0 and not no_buffer:
             sol_capacity = 1
         if sol_capacity > 0 and prob.n > 0:
             buf = torch.empty((sol_capacity, prob.n), dtype=torch.int32, device=self.torch_device)
@@ -366,16 +367,31 @@ class Context:
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
                     explore_pm: int = 0, seed: int = 0, use_graph: bool = False,
-                    two_way: bool = False):
-        """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records."""
+                    two_way: bool = False, sol_out=None):
+        """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records.
+        sol_out: optional int32 cuda tensor [B, >= max n]; FIRST mode stores
+        instance b's solution in row b (no per-instance buffers, and the
+        results carry no solutions: read them from sol_out)."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()
         bufs = []
+        if sol_out is not None:
+            if mode != MODE_FIRST or sol_out.dtype != _torch().int32 or sol_out.dim() != 2 \
+                    or sol_out.shape[0] < B or sol_out.shape[1] < max(p.n for p in probs) \
+                    or not sol_out.is_cuda or not sol_out.is_contiguous():
+                raise ValueError("sol_out: FIRST mode and a contiguous int32 cuda tensor [B, max n]")
+            row = sol_out.shape[1] * 4
+            base = sol_out.data_ptr()
         for b, p in enumerate(probs):
             L, buf = self._limits(p, mode, max_nodes, max_solutions, time_ms, branching, layout,
-                                  split_target, sol_capacity, workers, donate, policy, 0,
-                                  trace if b == 0 else None, explore_pm, seed, use_graph, two_way)
+                                  split_target, 0 if sol_out is not None else sol_capacity,
+                                  workers, donate, policy, 0,
+                                  trace if b == 0 else None, explore_pm, seed, use_graph, two_way,
+                                  no_buffer=sol_out is not None)
+            if sol_out is not None:
+                L.sol_buf = base + b * row
+                L.sol_capacity = 1
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()
