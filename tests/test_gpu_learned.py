@@ -110,6 +110,37 @@ def test_learned_policy_keeps_counts_and_verdicts(ctx, cb):
     assert sorted(map(tuple, r.solutions.tolist())) == sorted(map(tuple, ref.solutions.tolist()))
 
 
+def _first_fail_policy():
+    """A closed-form network: one live hidden unit reading feature 0
+    (|D_i| / d_i) with weight 1, output weight 1, every other parameter 0.
+    Its prediction is the domain fraction itself (bf16-exact when d is 8 or
+    16, and strictly increasing in |D_i| for any one d), so on instances
+    whose variables share one domain size its argmin (lowest index on ties)
+    is the first-fail choice."""
+    th = np.zeros(M.NP, dtype=np.float32)
+    th[M.OFF_W1 + 0 * M.F + 0] = 1.0
+    th[M.OFF_W2 + 0] = 1.0
+    return th
+
+
+@pytest.mark.parametrize("inst_fn", [lambda: cspgen.queens(8), lambda: cspgen.queens(10),
+                                     lambda: cspgen.rb(5, n=16, d=16, dens_pm=350, tight_pm=560),
+                                     lambda: cspgen.rb(6, n=18, d=8, dens_pm=350, tight_pm=410)],
+                         ids=["queens8", "queens10", "rb_d16", "rb_d8"])
+def test_closed_form_policy_is_first_fail(ctx, cb, inst_fn):
+    """The fused in-kernel network and argmin pick exactly the first-fail
+    variable: node and failure counts equal the oracle's first-fail search,
+    with one worker and with the device full of workers."""
+    inst = inst_fn()
+    assert len(set(int(x) for x in inst.dsize)) == 1
+    pol = cb.Policy(ctx, _first_fail_policy())
+    ref = oracle.solve(inst, oracle.MODE_COUNT)
+    prob = ctx.load(inst)
+    for kw in ({"workers": 1}, {}):
+        r = ctx.solve(prob, cb.MODE_COUNT, branching=cb.BRANCH_LEARNED, policy=pol, **kw)
+        assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails), kw
+
+
 def test_trace_collection_and_training(ctx, cb):
     from paper_1909_09213_amd import learn
     insts = learn.instances(base=cspgen.SEED_TRAIN, count=256)

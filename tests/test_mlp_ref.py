@@ -1,6 +1,7 @@
-"""Pins of the fp64 reference of the branching network: central differences,
-bf16 rounding against its IEEE definition and torch's converter, and the
-closed form of Adam's first step."""
+"""Pins of the fp64 reference of the branching network: central differences
+(exact network, and the bf16 network at a point where its rounding is the
+identity), bf16 rounding against its IEEE definition and torch's converter,
+and the closed form of Adam's first step."""
 import numpy as np
 import torch
 
@@ -69,3 +70,42 @@ def test_quantized_forward_close_to_exact():
     yq, _, _ = M.forward(th, X, True)
     ye, _, _ = M.forward(th, X, False)
     assert np.max(np.abs(yq - ye)) < 0.05 * (1 + np.max(np.abs(ye)))
+
+
+def test_quantized_gradient_at_bf16_exact_point():
+    """grad(quantized=True) treats the bf16 rounding of weights, inputs and
+    hidden activations as the identity.  At a point where every one of those
+    values is already a bf16 number the rounding IS the identity, so there
+    the straight-through gradient must equal the true derivative of the
+    loss, measured by central differences of the exact network."""
+    rng = np.random.default_rng(6)
+    th = np.zeros(M.NP)
+    # quarters, sixteenths and eighths: every weight, input and
+    # pre-activation (|pre| <= 6.5, a multiple of 1/16) has at most 8
+    # significant bits, so it is a bf16 number
+    th[M.OFF_W1:M.OFF_B1] = rng.integers(-4, 5, M.H * M.F) / 4.0
+    th[M.OFF_B1:M.OFF_W2] = rng.integers(-8, 9, M.H) / 16.0
+    th[M.OFF_W2:M.OFF_B2] = rng.integers(-4, 5, M.H) / 8.0
+    th[M.OFF_B2] = 0.125
+    X = rng.integers(0, 5, (200, M.F)) / 4.0
+    W1, b1, w2, _ = M.unpack(th)
+    for a in (W1, b1, w2, X):
+        assert np.array_equal(M.bf16_round(a), a)
+    _, pre, Hact = M.forward(th, X, quantized=False)
+    assert np.array_equal(M.bf16_round(Hact), Hact)
+    # rows away from the ReLU kink (a step of 1e-4 never crosses it)
+    X = X[np.min(np.abs(pre), axis=1) >= 1.0 / 16][:60]
+    assert X.shape[0] >= 20
+    T = rng.integers(-16, 17, X.shape[0]) / 8.0
+    yq, _, _ = M.forward(th, X, quantized=True)
+    ye, _, _ = M.forward(th, X, quantized=False)
+    assert np.array_equal(yq, ye)
+    g = M.grad(th, X, T, quantized=True)
+    h = 1e-4
+    num = np.zeros(M.NP)
+    for i in range(M.NP):
+        e = np.zeros(M.NP)
+        e[i] = h
+        num[i] = (M.loss(th + e, X, T, False) - M.loss(th - e, X, T, False)) / (2 * h)
+    err = np.abs(g - num) / np.maximum(1e-3, np.abs(num))
+    assert err.max() < 1e-6

@@ -225,6 +225,16 @@ def test_alldiff_permutation_count(k, s):
     r = oracle.solve(inst, oracle.MODE_COUNT)
     assert r.count == math.factorial(s) // math.factorial(s - k)
     assert r.fails == 0  # singleton elimination never fails here
+    # Node count in closed form.  All domains stay equal: after j labelings
+    # singleton elimination leaves s - j values to every unlabelled variable,
+    # so first-fail labels the variables in index order and level j of the
+    # tree holds s!/(s-j)! nodes.  The last level exists only if the last
+    # variable still has two values (s > k); with s = k it is a singleton
+    # once the other k - 1 are labelled, and those nodes are the solutions.
+    # A propagator without singleton elimination would branch on s values at
+    # every level and fail on the repeated ones.
+    perm = [math.factorial(s) // math.factorial(s - j) for j in range(k + 1)]
+    assert r.nodes == (sum(perm) if s > k else sum(perm[:k]))
 
 
 @pytest.mark.parametrize("k", [2, 3, 5, 8])
