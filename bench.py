@@ -251,6 +251,7 @@ def main():
         chosen, div, rates = ctx.autotune(probs, cb.MODE_FIRST, time_ms=400, rates=True,
                                           max_nodes=args.budget)
         tuned = {"chosen": names[chosen], "worker_divisor": div,
+                 "active_per_xcd": ctx.last_active_per_xcd,
                  "nodes_per_ms": {f"{names[k]}/{d}": round(v) for (k, d), v in rates.items()}}
     t_setup = time.perf_counter() - t_setup
 

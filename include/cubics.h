@@ -135,6 +135,14 @@ typedef struct {
                                 1 = 2-way branching: x = a, then x != a, with a the
                                 smallest value of the branching variable (the same
                                 solutions, another tree: other node counts) */
+    int32_t active_per_xcd;  /* batches: k > 0 = one work queue per XCD (8 on MI355X)
+                                holding k instances at a time, the next instance admitted
+                                to a queue when one of its instances ends, so that the
+                                tables an XCD's workers read stay in its L2 (used when
+                                B > 8 and the launch has at least 8 workgroups);
+                                -1 = every instance queued at launch on one queue;
+                                0 = the autotuned choice for the batch's shape (layout
+                                AUTO), else one queue */
 } cubics_limits;
 
 typedef struct {
@@ -244,15 +252,20 @@ int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
    hand-offs cost less), measure search nodes per ms, and remember the fastest
    pair (a smaller worker count of the same layout must be 5% faster to win)
    for the first problem's shape bucket (domain words, domain size,
-   variable count, constraint kinds).  Later solves with layout AUTO and
-   workers 0 on the same context use it.  *chosen and *chosen_div (nullable)
-   receive the layout and the divisor; rates (nullable, host,
-   3 * CUBICS_AUTOTUNE_DIVS doubles) receives the measured nodes per ms at
-   [(layout - 1) * CUBICS_AUTOTUNE_DIVS + divisor index], 0 where a layout is
-   not admitted.  The runs use limits[] (NULL: none) with time_ms added. */
+   variable count, constraint kinds).  For a batch (B > 8) it then tries one
+   queue per XCD with 4, 8, 16 and 32 instances active on each (see
+   active_per_xcd), kept if 5% faster than one queue.  Later solves with
+   layout AUTO, workers 0 and active_per_xcd 0 on the same context use the
+   choice.  *chosen, *chosen_div and *chosen_active (nullable) receive the
+   layout, the divisor and the instances per XCD (0 = one queue); rates
+   (nullable, host, 3 * CUBICS_AUTOTUNE_DIVS doubles) receives the measured
+   nodes per ms at [(layout - 1) * CUBICS_AUTOTUNE_DIVS + divisor index]
+   (one queue), 0 where a layout is not admitted.  The runs use limits[]
+   (NULL: none) with time_ms added. */
 enum { CUBICS_AUTOTUNE_DIVS = 3 };
 int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
-                    int64_t time_ms, int32_t *chosen, int32_t *chosen_div, double *rates);
+                    int64_t time_ms, int32_t *chosen, int32_t *chosen_div, int32_t *chosen_active,
+                    double *rates);
 
 /* ------------------------------------------- large-neighbourhood search
  * Minimise sum_i obj[i] * x_i (every obj[i] >= 0, at least one > 0) over the

@@ -93,6 +93,7 @@ struct cubics_ctx {
     struct Tuned {
         int layout;  // revision layout
         int div;     // workers = the occupancy-limited maximum / div
+        int gang;    // batches: instances active per XCD ring (0 = one queue)
     };
     std::map<std::string, Tuned> tuned;  // shape bucket -> autotuned choice
     std::map<std::string, hipGraphExec_t> graphs;  // captured launch sequences
@@ -561,6 +562,7 @@ extern "C" int cubics_prob_info(const cubics_prob *p, int32_t *n, int32_t *W, in
 // ------------------------------------------------------------ solve support
 int policy_fill(const cubics_policy *pol, PolicyDev *out);
 
+
 namespace {
 
 int pow2_ge(int x) {
@@ -691,12 +693,19 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     HIPCHK(search_occupancy(G.wmax, &bpc, wpb, lds, tl, variant));
     if (bpc < 1) bpc = 1;
     int div = 1;
+    // instances active per XCD ring: the caller's, else (0) the autotuned
+    // one for an AUTO layout, else (-1, or nothing tuned) one queue
+    int gang = L0.active_per_xcd;
     if (worker_div > 0) {
         div = worker_div;
     } else if (L0.layout == CUBICS_LAYOUT_AUTO) {
         auto it = ctx->tuned.find(probs[0]->bucket);
-        if (it != ctx->tuned.end()) div = it->second.div;
+        if (it != ctx->tuned.end()) {
+            div = it->second.div;
+            if (gang == 0) gang = it->second.gang;
+        }
     }
+    if (gang < 0) gang = 0;
     int nworkers = L0.workers > 0 && worker_div == 0 ? L0.workers : std::max(1, bpc * wpb * ctx->cu_count / div);
 
     // ---- buffers
@@ -709,18 +718,41 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     const uint32_t trail_words = (uint32_t)trail_words64;
     // at most 16 GiB of trail stacks: fewer workers for very deep trails
     nworkers = (int)std::min<int64_t>(nworkers, std::max<int64_t>(1, (16LL << 30) / (4 * trail_words64)));
+    // one ring per XCD for a batch when asked for (active_per_xcd > 0) and
+    // every ring gets workgroups; else one ring holding every instance
+    const auto ring_count = [&](int nw_) {
+        return (gang > 0 && B > MAX_RINGS && (nw_ + wpb - 1) / wpb >= MAX_RINGS) ? MAX_RINGS : 1;
+    };
+    // queue cells per ring for the workers' donations and the eager split
+    const auto queue_cells = [&](int nw_) {
+        const int R = ring_count(nw_);
+        const long long roots = R == 1 ? B : std::min<long long>(B, gang);
+        long long want = roots + 2LL * ((nw_ + R - 1) / R) + 2LL * L0.split_target + 1024;
+        if (want > (1LL << 26)) want = 1LL << 26;
+        uint32_t c = 4096;
+        while ((long long)c < want) c *= 2;
+        return c;
+    };
     const int blocks = (nworkers + wpb - 1) / wpb;
-    long long want = (long long)B + 2LL * nworkers + 2LL * L0.split_target + 1024;
-    if (want > (1LL << 26)) want = 1LL << 26;
-    uint32_t cap = 4096;
-    while ((long long)cap < want) cap *= 2;
+    const uint32_t cap = queue_cells(nworkers);  // per ring
+    const int nrings = ring_count(nworkers);
+    const size_t cells = (size_t)cap * nrings;
+    void *d_inst, *d_ctl, *d_q, *d_qseq, *d_qdata, *d_trail;
     int rc;
-    if ((rc = ctx->inst.ensure(sizeof(InstDev) * (size_t)B))) return rc;
-    if ((rc = ctx->ctl.ensure(sizeof(InstCtl) * (size_t)B))) return rc;
-    if ((rc = ctx->q.ensure(sizeof(QCtl)))) return rc;
-    if ((rc = ctx->qseq.ensure(4ull * cap))) return rc;
-    if ((rc = ctx->qdata.ensure(4ull * cap * slot_words))) return rc;
-    if ((rc = ctx->trail.ensure(4ull * trail_words * (size_t)nworkers))) return rc;
+    {
+        if ((rc = ctx->inst.ensure(sizeof(InstDev) * (size_t)B))) return rc;
+        if ((rc = ctx->ctl.ensure(sizeof(InstCtl) * (size_t)B))) return rc;
+        if ((rc = ctx->q.ensure(sizeof(QBlock)))) return rc;
+        if ((rc = ctx->qseq.ensure(4ull * cells))) return rc;
+        if ((rc = ctx->qdata.ensure(4ull * cells * slot_words))) return rc;
+        if ((rc = ctx->trail.ensure(4ull * trail_words * (size_t)nworkers))) return rc;
+        d_inst = ctx->inst.p;
+        d_ctl = ctx->ctl.p;
+        d_q = ctx->q.p;
+        d_qseq = ctx->qseq.p;
+        d_qdata = ctx->qdata.p;
+        d_trail = ctx->trail.p;
+    }
 
     std::vector<InstDev> inst(B);
     for (int b = 0; b < B; ++b) {
@@ -732,23 +764,27 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         inst[b].max_solutions = Lb.max_solutions;
         if (mode == CUBICS_MODE_FIRST && inst[b].sol_cap > 1) inst[b].sol_cap = 1;
     }
-    HIPCHK(hipMemcpyAsync(ctx->inst.p, inst.data(), sizeof(InstDev) * B, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_inst, inst.data(), sizeof(InstDev) * B, hipMemcpyHostToDevice, st));
 
     SearchParams P;
     memset(&P, 0, sizeof P);
-    P.inst = (const InstDev *)ctx->inst.p;
-    P.ctl = (InstCtl *)ctx->ctl.p;
+    P.inst = (const InstDev *)d_inst;
+    P.ctl = (InstCtl *)d_ctl;
     P.B = B;
     P.mode = mode;
     P.layout = layout;
     P.branching = L0.branching;
     P.two_way = L0.two_way;
-    P.q = (QCtl *)ctx->q.p;
-    P.qseq = (uint32_t *)ctx->qseq.p;
-    P.qdata = (uint32_t *)ctx->qdata.p;
+    P.qb = (QBlock *)d_q;
+    P.q = &P.qb->ring[0];
+    P.g = &P.qb->g;
+    P.nrings = nrings;
+    P.seeded = nrings > 1 ? gang : B;
+    P.qseq = (uint32_t *)d_qseq;
+    P.qdata = (uint32_t *)d_qdata;
     P.qmask = cap - 1;
     P.slot_words = slot_words;
-    P.trail = (uint32_t *)ctx->trail.p;
+    P.trail = (uint32_t *)d_trail;
     P.frame_words = frame_words;
     P.trail_words = trail_words;
     P.max_frames = (int32_t)frames;
@@ -806,11 +842,11 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         HIPCHK(hipEventRecord(ctx->ev1, st));
     }
     std::vector<InstCtl> ctl(B);
-    QCtl qh;
+    QGlobal qh;
     unsigned long long ntraces = 0;
     if (P.trace_out) HIPCHK(hipMemcpyAsync(&ntraces, ctx->tracecnt.p, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(ctl.data(), ctx->ctl.p, sizeof(InstCtl) * B, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&qh, ctx->q.p, sizeof(QCtl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(ctl.data(), d_ctl, sizeof(InstCtl) * B, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&qh, &((QBlock *)d_q)->g, sizeof(QGlobal), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     float kms = 0.f;
     HIPCHK(hipEventElapsedTime(&kms, ctx->ev0, ctx->ev1));
@@ -866,7 +902,8 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
 }
 
 extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
-                               int64_t time_ms, int32_t *chosen, int32_t *chosen_div, double *rates) {
+                               int64_t time_ms, int32_t *chosen, int32_t *chosen_div, int32_t *chosen_active,
+                               double *rates) {
     if (!probs || B < 1 || !probs[0] || time_ms < 1) return fail(CUBICS_EINVAL, "bad autotune arguments");
     bool seg_ok = true, var_ok = true;
     for (int b = 0; b < B; ++b) {
@@ -885,10 +922,12 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
         lim[b].use_graph = 0;
     }
     lim[0].time_ms = time_ms;
+    lim[0].active_per_xcd = -1;  // layouts and worker counts are compared on one queue
     std::vector<cubics_result> res(B);
     if (rates)
         for (int k = 0; k < 3 * CUBICS_AUTOTUNE_DIVS; ++k) rates[k] = 0.0;
-    cubics_ctx::Tuned best = {CUBICS_LAYOUT_LANE, 1};
+    cubics_ctx::Tuned best = {CUBICS_LAYOUT_LANE, 1, 0};
+    const int tune_mode = mode == CUBICS_MODE_FIRST ? CUBICS_MODE_FIRST : CUBICS_MODE_COUNT;
     double best_rate = -1.0;
     int cands[3], nc = 0;
     cands[nc++] = CUBICS_LAYOUT_LANE;
@@ -900,8 +939,7 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
         for (int di = 0; di < CUBICS_AUTOTUNE_DIVS; ++di) {
             // a warm-up run, then the timed one
             for (int rep = 0; rep < 2; ++rep) {
-                int rc = solve_impl(probs, B, mode == CUBICS_MODE_FIRST ? CUBICS_MODE_FIRST : CUBICS_MODE_COUNT,
-                                    lim.data(), res.data(), divs[di]);
+                int rc = solve_impl(probs, B, tune_mode, lim.data(), res.data(), divs[di]);
                 if (rc) return rc;
             }
             uint64_t nodes = 0;
@@ -913,13 +951,43 @@ extern "C" int cubics_autotune(cubics_prob *const *probs, int32_t B, int32_t mod
             const double need = (best_rate > 0 && di > 0 && cands[ci] == best.layout) ? 1.05 : 1.0;
             if (rate > best_rate * need) {
                 best_rate = rate;
-                best = {cands[ci], divs[di]};
+                best = {cands[ci], divs[di], 0};
+            }
+        }
+    }
+    // batches: one ring per XCD with a few instances active on each, for
+    // the chosen layout and worker count (5% better than one queue to win).
+    // Rings pay off over a whole launch (their instances first spread over
+    // an XCD's workers), so when every instance has a node budget each
+    // candidate runs to completion instead of for time_ms.
+    if (B > MAX_RINGS) {
+        bool budgeted = true;
+        for (int b = 0; b < B; ++b) budgeted &= lim[b].max_nodes > 0;
+        static const int gangs[] = {-1, 4, 8, 16, 32};
+        lim[0].layout = best.layout;
+        if (budgeted) lim[0].time_ms = 0;
+        double base_rate = 0.0;
+        for (int g : gangs) {
+            lim[0].active_per_xcd = g;
+            for (int rep = 0; rep < (budgeted ? 1 : 2); ++rep) {
+                int rc = solve_impl(probs, B, tune_mode, lim.data(), res.data(), best.div);
+                if (rc) return rc;
+            }
+            uint64_t nodes = 0;
+            for (int b = 0; b < B; ++b) nodes += res[b].nodes;
+            const double rate = (double)nodes / std::max(res[0].kernel_ms, 1e-3);
+            if (g < 0) {
+                base_rate = best_rate = rate;
+            } else if (rate > std::max(best_rate, 1.05 * base_rate)) {
+                best_rate = rate;
+                best.gang = g;
             }
         }
     }
     probs[0]->ctx->tuned[probs[0]->bucket] = best;
     if (chosen) *chosen = best.layout;
     if (chosen_div) *chosen_div = best.div;
+    if (chosen_active) *chosen_active = best.gang;
     return CUBICS_OK;
 }
 

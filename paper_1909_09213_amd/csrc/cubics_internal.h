@@ -79,19 +79,32 @@ struct InstCtl {
     int32_t done;     // 1 = stop working on this instance
     int32_t reason;   // 0 none, 1 first found, 2 node limit, 3 cap
     int32_t found;    // FIRST mode winner flag
-    int32_t pad;
+    int32_t live;     // the instance's tasks queued or running (rings > 1)
 };
 
-// Work-queue control block: each hot word on its own 128-byte line.
+// Control of one work-queue ring: each hot word on its own 128-byte line.
 struct QCtl {
     uint32_t head; uint32_t _p0[31];
     uint32_t tail; uint32_t _p1[31];
-    int32_t pending; int32_t _p2[31];
-    // idle workers (bits 0..23) | SIG_DONE | SIG_STOP: the one word a busy
-    // worker polls; the rest is read only when it is non-zero
+    // idle workers of the ring (bits 0..23) | SIG_DONE | SIG_STOP: the one
+    // word a busy worker polls; the rest is read only when it is non-zero
     uint32_t signal; int32_t _p3[31];
+};
+// Launch-wide control.
+struct QGlobal {
+    int32_t pending; int32_t _p2[31];       // tasks queued or running, all rings
     unsigned long long produced; uint32_t _p4[30];
     int32_t stop; int32_t stop_reason; uint32_t _p5[30];
+    uint32_t next_inst; uint32_t _p6[31];   // next instance to admit (rings > 1)
+};
+// A batch runs on one ring, or on one ring per XCD (workgroup b serves ring
+// b % MAX_RINGS; the hardware deals workgroups to the 8 XCDs in turn), each
+// ring holding a few instances at a time, so that the tables one XCD's
+// workers read stay in that XCD's L2.
+constexpr int MAX_RINGS = 8;
+struct QBlock {
+    QGlobal g;
+    QCtl ring[MAX_RINGS];
 };
 
 constexpr uint32_t SIG_IDLE_MASK = 0x00FFFFFFu;
@@ -129,10 +142,14 @@ struct SearchParams {
     int32_t layout;      // 1 LANE, 2 SEG
     int32_t branching;
     int32_t two_way;     // 2-way branching: x = min D_x, then x != min D_x
-    QCtl *q;
-    uint32_t *qseq;
-    uint32_t *qdata;
-    uint32_t qmask;
+    QBlock *qb;
+    QCtl *q;             // the worker's ring (the kernel points it at ring b % nrings)
+    QGlobal *g;
+    int32_t nrings;      // 1, or MAX_RINGS with admission of instances per ring
+    int32_t seeded;      // instances queued per ring at launch (rings > 1)
+    uint32_t *qseq;      // [nrings][qmask + 1] (the kernel offsets it per ring)
+    uint32_t *qdata;     // [nrings][qmask + 1][slot_words]
+    uint32_t qmask;      // cells per ring - 1
     uint32_t slot_words;
     uint32_t *trail;
     uint32_t frame_words;

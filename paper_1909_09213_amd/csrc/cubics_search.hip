@@ -974,6 +974,18 @@ DEV int node_test(const InstDev &I, const Lds &L, int lane, int *bx) {
 // a producer publishes it.  Compare-and-swap pops made every polling wave
 // race for each new task, a storm of atomics on one word per hand-over that
 // capped hand-overs at a few 10^4 per second in a search's tail.
+// Flags every ring's signal word (lane 0 only): SIG_DONE when an instance's
+// done flag was set, SIG_STOP when the whole launch stops.
+DEV void signal_rings(const SearchParams &P, uint32_t bit) {
+    for (int r = 0; r < P.nrings; ++r) or_u(&P.qb->ring[r].signal, bit);
+}
+// Stop the launch (lane 0 only): reason 2 time limit, 3 cancelled, 4 trail overflow.
+DEV void stop_launch(const SearchParams &P, int reason) {
+    P.g->stop_reason = reason;
+    st_rel_i(&P.g->stop, 1);
+    signal_rings(P, SIG_STOP);
+}
+
 DEV bool q_reserve(const SearchParams &P, uint32_t *cell, uint32_t *posout) {
     uint32_t pos = ld_rlx(&P.q->tail);
     for (;;) {
@@ -1003,9 +1015,11 @@ DEV bool push_frame(const SearchParams &P, int inst, int x, int depth, const uin
     uint32_t cell = 0, pos = 0;
     int ok = 0;
     if (lane == 0) {
-        add_i(&P.q->pending, 1);
+        add_i(&P.g->pending, 1);
         ok = q_reserve(P, &cell, &pos) ? 1 : 0;
-        if (!ok) add_i(&P.q->pending, -1);
+        if (!ok) add_i(&P.g->pending, -1);
+        // the instance's live tasks count it before it is published
+        if (ok && P.nrings > 1) add_i(&P.ctl[inst].live, 1);
     }
     ok = uni(ok);
     if (!ok) return false;
@@ -1043,11 +1057,7 @@ struct Frame {  // cached top-of-trail frame
 // (the host sizes the trail for the deepest path, so this never fires).
 DEV bool trail_full(const SearchParams &P, int sp, int lane) {
     if (sp < P.max_frames) return false;
-    if (lane == 0) {
-        P.q->stop_reason = 4;
-        st_rel_i(&P.q->stop, 1);
-        or_u(&P.q->signal, SIG_STOP);
-    }
+    if (lane == 0) stop_launch(P, 4);
     return true;
 }
 
@@ -1097,7 +1107,7 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
                 add_u64(&ctl->count, 1ull);
                 ctl->reason = 1;
                 st_rel_i(&ctl->done, 1);
-                or_u(&P.q->signal, SIG_DONE);
+                signal_rings(P, SIG_DONE);
             }
         }
         return;
@@ -1119,7 +1129,7 @@ DEV void record_solution(const SearchParams &P, const InstDev &I, InstCtl *ctl, 
         if (I.max_solutions && slot + 1 >= I.max_solutions && lane == 0) {
             ctl->reason = 3;
             st_rel_i(&ctl->done, 1);
-            or_u(&P.q->signal, SIG_DONE);
+            signal_rings(P, SIG_DONE);
         }
     } else {
         C.sols += 1;
@@ -1163,6 +1173,19 @@ DEV void flush(InstCtl *ctl, Counters &C, int lane) {
 // 512).
 constexpr int POLL = 128;
 constexpr int POLL_VAR = 2048;
+// The LDS layouts also poll once POLL_TICKS of wall clock (100 MHz ticks)
+// have passed since the last poll, after at least POLL_MIN nodes, and under
+// a node budget they count their nodes against it every ACCT_TICKS: when a
+// node takes a hundred microseconds (instances of a hundred variables and
+// thousands of table revisions per node), 128 nodes are tens of
+// milliseconds, during which idle workers wait for a donation, and an
+// instance shared by dozens of workers runs thousands of nodes past its
+// budget.  (A clock-based poll every 50 us made the fast nodes of small
+// count searches donate so often that their tails split into tiny tasks:
+// 200 instances of 12-18 variables took 4.7 s instead of 0.6 s.)
+constexpr int POLL_MIN = 8;
+constexpr long long POLL_TICKS = 100000;
+constexpr long long ACCT_TICKS = 5000;
 
 
 // ------------------------------------------------------ branching policy
@@ -1294,6 +1317,8 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     bool snap_valid = false;
     int depth = F0.depth;
     int since_poll = 0, polls = 0;
+    // clock of the task's last poll (a task starts as if it had just polled)
+    long long last_poll = (long long)wall_clock64(), last_acct = last_poll;
     int open_x = 0;
     const bool tracing = FEAT == 2 && P.trace_out != nullptr;
     const bool learned = FEAT == 1 && P.branching == 1;
@@ -1352,7 +1377,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             bool split = false;
             if (P.split_target > 0) {
                 long long prod = 0;
-                if (lane == 0) prod = (long long)ld_rlx_u64(&P.q->produced);
+                if (lane == 0) prod = (long long)ld_rlx_u64(&P.g->produced);
                 prod = unill(prod);
                 if (prod < P.split_target) split = true;
             }
@@ -1400,7 +1425,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                         }
                     }
                 }
-                if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
+                if (lane == 0 && pushed) add_u64(&P.g->produced, (u64)pushed);
                 if (tracing && pushed)
                     for (int t = lane; t < sp; t += 64) trail[(size_t)t * FW + 2] = 1u;
                 bool left = false;
@@ -1557,9 +1582,21 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 }
             }
         }
-        // periodic checks: stop flags, limits, donation
-        if (++since_poll >= POLL) {
-            since_poll = 0;
+        // periodic checks: stop flags and the node budget (every POLL nodes,
+        // and under a budget also every POLL_TICKS), then the clock, the
+        // cancel flag and donation (every POLL nodes only: donating more
+        // often splits a search's tail into too many small tasks)
+        ++since_poll;
+        bool due = since_poll >= POLL, acct = due;
+        if (!due && since_poll >= POLL_MIN) {
+            const long long now = (long long)wall_clock64();
+            due = now - last_poll >= POLL_TICKS;
+            acct = due || (I.max_nodes && now - last_acct >= ACCT_TICKS);
+        }
+        if (acct) {
+            const long long now = (long long)wall_clock64();
+            last_acct = now;
+            if (due) last_poll = now;
             // one shared word per poll; stop, done and queue words only when
             // it says so
             int stop = 0, want = 0;
@@ -1569,7 +1606,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 // donate while fewer tasks wait unclaimed than waves are idle
                 // (a negative difference: tickets waiting for a task)
                 const int idle = (int)(sig & SIG_IDLE_MASK);
-                if (P.donate && idle > 0)
+                if (due && P.donate && idle > 0)
                     want = (int)(ld_rlx(&P.q->tail) - ld_rlx(&P.q->head)) < idle;
             }
             stop = uni(stop);
@@ -1580,10 +1617,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 tot = uni64(tot);
                 C.nodes = 0;
                 if (tot >= I.max_nodes) {
-                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); or_u(&P.q->signal, SIG_DONE); }
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); signal_rings(P, SIG_DONE); }
                     return;
                 }
             }
+            if (due) {
+            since_poll = 0;
             // the clock and the host's cancel flag (a read over PCIe) every
             // 16th poll
             if ((P.time_ticks || P.cancel) && (++polls & 15) == 0) {
@@ -1591,11 +1630,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
                     if (P.cancel && *P.cancel) st2 = 3;
-                    if (st2) {
-                        P.q->stop_reason = st2;
-                        st_rel_i(&P.q->stop, 1);
-                        or_u(&P.q->signal, SIG_STOP);
-                    }
+                    if (st2) stop_launch(P, st2);
                 }
                 if (uni(st2)) return;
             }
@@ -1634,6 +1669,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                     }
                 }
             }
+            }  // due
         }
     }
 }
@@ -1850,7 +1886,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
             bool split = false;
             if (P.split_target > 0) {
                 long long prod = 0;
-                if (lane == 0) prod = (long long)ld_rlx_u64(&P.q->produced);
+                if (lane == 0) prod = (long long)ld_rlx_u64(&P.g->produced);
                 prod = unill(prod);
                 if (prod < P.split_target) split = true;
             }
@@ -1888,7 +1924,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                         ++pushed;
                     }
                 }
-                if (lane == 0 && pushed) add_u64(&P.q->produced, (u64)pushed);
+                if (lane == 0 && pushed) add_u64(&P.g->produced, (u64)pushed);
                 if (!rem) goto next_child;
                 dx = rem;
             }
@@ -2016,7 +2052,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 tot = uni64(tot);
                 C.nodes = 0;
                 if (tot >= I.max_nodes) {
-                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); or_u(&P.q->signal, SIG_DONE); }
+                    if (lane == 0) { ctl->reason = 2; st_rel_i(&ctl->done, 1); signal_rings(P, SIG_DONE); }
                     return;
                 }
             }
@@ -2027,11 +2063,7 @@ DEV void run_task_var(const SearchParams &P, const InstDev &I, InstCtl *ctl, int
                 if (lane == 0) {
                     if (P.time_ticks && (long long)wall_clock64() - t_start > P.time_ticks) st2 = 2;
                     if (P.cancel && *P.cancel) st2 = 3;
-                    if (st2) {
-                        P.q->stop_reason = st2;
-                        st_rel_i(&P.q->stop, 1);
-                        or_u(&P.q->signal, SIG_STOP);
-                    }
+                    if (st2) stop_launch(P, st2);
                 }
                 if (uni(st2)) return;
             }
@@ -2163,9 +2195,18 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     }
     L.scr = base + off;  // the rest of the worker's words
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
+    // the workgroup's ring (with one ring per XCD, workgroup b runs on XCD
+    // b % 8, as the hardware deals workgroups out in turn)
+    const int ring = P.nrings > 1 ? (int)(blockIdx.x % (unsigned)P.nrings) : 0;
+    P.q = &P.qb->ring[ring];
+    P.qseq += (size_t)ring * (P.qmask + 1u);
+    P.qdata += (size_t)ring * (P.qmask + 1u) * P.slot_words;
     const long long t_start = (long long)wall_clock64();
     Counters C = {};
     bool idle = false;
+    // an instance this worker admitted (rings > 1): its ROOT task runs next,
+    // on this worker, without passing through the queue
+    int direct = -1;
     // Idle waves: only the one holding its workgroup's token takes a ticket
     // and waits on its cell (backing off exponentially, up to ~27 us between
     // polls); the others wait on the token in LDS.  A wave holding a ticket
@@ -2177,64 +2218,74 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
     uint32_t ticket = 0;
     for (;;) {
         uint32_t cell = 0, pos = 0;
-        int got = 0, fin = 0;
-        if (!poller) {
-            int t = 0;
-            if (lane == 0) t = lds_take(&idle_token) ? 1 : 0;
-            poller = uni(t);
-            if (poller) backoff = 1;
-        }
-        if (poller) {
-            if (!have_ticket) {
-                if (lane == 0) ticket = add_u(&P.q->head, 1u);
-                ticket = uniu(ticket);
-                have_ticket = 1;
-                polls = 0;
-            }
-            if (lane == 0) {
-                got = ld_rlx(&P.qseq[ticket & P.qmask]) == ticket + 1u;
-                if (!got && (++polls & 1) == 0 && ld_rlx_i(&P.q->pending) == 0) {
-                    fin = 1;
-                    lds_st(&drained, 1u);
-                }
-            }
-            got = uni(got);
-        } else if (lane == 0) {
-            fin = lds_ld(&drained) != 0u;
-        }
-        if (!got) {
-            if (lane == 0 && !idle) add_u(&P.q->signal, 1u);
-            idle = true;
-            if (uni(fin)) break;
-            if (poller) {
-                for (int s = 0; s < backoff; ++s) __builtin_amdgcn_s_sleep(32);
-                backoff = backoff < 32 ? backoff * 2 : 32;
-            } else {
-                __builtin_amdgcn_s_sleep(16);
-            }
-            continue;
-        }
-        slot_claimed();
-        pos = ticket;
-        cell = ticket & P.qmask;
-        have_ticket = 0;
-        if (lane == 0) lds_st(&idle_token, 0u);  // hand the token on
-        poller = 0;
-        backoff = 1;
-        if (idle) {
-            if (lane == 0) add_u(&P.q->signal, 0xFFFFFFFFu);  // idle - 1
-            idle = false;
-        }
-        uint32_t *s = P.qdata + (size_t)cell * P.slot_words;
-        const uint32_t hw = lane < SLOT_HDR ? ld_rlx(s + lane) : 0u;  // header word `lane`
-        const int b = __builtin_amdgcn_readlane((int)hw, 0);
-        const int kind = __builtin_amdgcn_readlane((int)hw, 1);
+        uint32_t *s = nullptr;
+        int b = 0, kind = K_ROOT;
         Frame<WM> F0;
-        F0.x = __builtin_amdgcn_readlane((int)hw, 2);
-        F0.depth = __builtin_amdgcn_readlane((int)hw, 3);
-        F0.side = __builtin_amdgcn_readlane((int)hw, 12);
+        F0.x = F0.depth = F0.side = 0;
 #pragma unroll
-        for (int k = 0; k < WM; ++k) F0.v[k] = (uint32_t)__builtin_amdgcn_readlane((int)hw, 4 + k);
+        for (int k = 0; k < WM; ++k) F0.v[k] = 0u;
+        if (direct >= 0) {
+            b = direct;
+            direct = -1;
+        } else {
+            int got = 0, fin = 0;
+            if (!poller) {
+                int t = 0;
+                if (lane == 0) t = lds_take(&idle_token) ? 1 : 0;
+                poller = uni(t);
+                if (poller) backoff = 1;
+            }
+            if (poller) {
+                if (!have_ticket) {
+                    if (lane == 0) ticket = add_u(&P.q->head, 1u);
+                    ticket = uniu(ticket);
+                    have_ticket = 1;
+                    polls = 0;
+                }
+                if (lane == 0) {
+                    got = ld_rlx(&P.qseq[ticket & P.qmask]) == ticket + 1u;
+                    if (!got && (++polls & 1) == 0 && ld_rlx_i(&P.g->pending) == 0) {
+                        fin = 1;
+                        lds_st(&drained, 1u);
+                    }
+                }
+                got = uni(got);
+            } else if (lane == 0) {
+                fin = lds_ld(&drained) != 0u;
+            }
+            if (!got) {
+                if (lane == 0 && !idle) add_u(&P.q->signal, 1u);
+                idle = true;
+                if (uni(fin)) break;
+                if (poller) {
+                    for (int z = 0; z < backoff; ++z) __builtin_amdgcn_s_sleep(32);
+                    backoff = backoff < 32 ? backoff * 2 : 32;
+                } else {
+                    __builtin_amdgcn_s_sleep(16);
+                }
+                continue;
+            }
+            slot_claimed();
+            pos = ticket;
+            cell = ticket & P.qmask;
+            have_ticket = 0;
+            if (lane == 0) lds_st(&idle_token, 0u);  // hand the token on
+            poller = 0;
+            backoff = 1;
+            if (idle) {
+                if (lane == 0) add_u(&P.q->signal, 0xFFFFFFFFu);  // idle - 1
+                idle = false;
+            }
+            s = P.qdata + (size_t)cell * P.slot_words;
+            const uint32_t hw = lane < SLOT_HDR ? ld_rlx(s + lane) : 0u;  // header word `lane`
+            b = __builtin_amdgcn_readlane((int)hw, 0);
+            kind = __builtin_amdgcn_readlane((int)hw, 1);
+            F0.x = __builtin_amdgcn_readlane((int)hw, 2);
+            F0.depth = __builtin_amdgcn_readlane((int)hw, 3);
+            F0.side = __builtin_amdgcn_readlane((int)hw, 12);
+#pragma unroll
+            for (int k = 0; k < WM; ++k) F0.v[k] = (uint32_t)__builtin_amdgcn_readlane((int)hw, 4 + k);
+        }
         const InstDev I = TL ? IL : P.inst[b];
         const int nw = I.n * I.W;
         if (kind == K_ROOT) {
@@ -2244,7 +2295,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         }
         wsync();
         // the slot's words are in LDS now: hand the cell back to producers
-        if (lane == 0) st_rlx(&P.qseq[cell], pos + P.qmask + 1u);
+        if (s && lane == 0) st_rlx(&P.qseq[cell], pos + P.qmask + 1u);
         InstCtl *ctl = P.ctl + b;
         int skip = 0;
         if (lane == 0) {
@@ -2259,7 +2310,21 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
         }
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
-        if (lane == 0) add_i(&P.q->pending, -1);
+        if (P.nrings > 1) {
+            // the instance's last task ended: admit the next instance into
+            // this ring (counted as pending before this task's end is)
+            int nb = -1;
+            if (lane == 0 && add_i(&ctl->live, -1) == 1) {
+                const uint32_t a = add_u(&P.g->next_inst, 1u);
+                if (a < (uint32_t)P.B) {
+                    nb = (int)a;
+                    add_i(&P.ctl[nb].live, 1);
+                    add_i(&P.g->pending, 1);
+                }
+            }
+            direct = uni(nb);
+        }
+        if (lane == 0) add_i(&P.g->pending, -1);
     }
     if (lane == 0 && idle) add_u(&P.q->signal, 0xFFFFFFFFu);
 }
@@ -2277,39 +2342,50 @@ __global__ void features_kernel(const InstDev *inst, const uint32_t *dom, int de
     }
 }
 
-// Reset the queue and seed it with one ROOT task per instance.
+// Reset the queue and seed it with ROOT tasks: every instance on one ring,
+// or, with one ring per XCD, the first `seeded` instances of each ring
+// (instance i on ring i % nrings); the rest are admitted as instances end.
 __global__ void init_kernel(SearchParams P) {
-    const uint32_t cap = P.qmask + 1u;
+    const uint32_t cells = P.qmask + 1u;
+    const uint32_t R = (uint32_t)P.nrings;
+    const uint32_t seeded = R == 1u ? (uint32_t)P.B : min((uint32_t)P.B, R * (uint32_t)P.seeded);
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t c = tid; c < cap; c += stride) {
-        if (c < (uint32_t)P.B) {
+    for (uint32_t c = tid; c < R * cells; c += stride) {
+        const uint32_t r = c / cells, local = c % cells;
+        const uint32_t on_ring = seeded > r ? (seeded - r + R - 1u) / R : 0u;
+        if (local < on_ring) {
             uint32_t *s = P.qdata + (size_t)c * P.slot_words;
-            s[0] = c;
+            s[0] = local * R + r;
             s[1] = (uint32_t)K_ROOT;
             s[2] = 0;
             s[3] = 0;
             for (int k = 0; k < 8 && 4 + k < SLOT_HDR; ++k) s[4 + k] = 0;
-            P.qseq[c] = c + 1u;
+            s[12] = 0;
+            P.qseq[c] = local + 1u;
         } else {
-            P.qseq[c] = c;
+            P.qseq[c] = local;
         }
     }
     for (uint32_t b = tid; b < (uint32_t)P.B; b += stride) {
         InstCtl z;
         z.count = z.n_slots = z.nodes = z.fails = z.revisions = z.alg_bytes = z.steals = z.tasks = 0;
-        z.done = z.reason = z.found = z.pad = 0;
+        z.done = z.reason = z.found = 0;
+        z.live = b < seeded ? 1 : 0;
         P.ctl[b] = z;
     }
     if (tid == 0 && P.trace_count) *P.trace_count = 0ull;
+    if (tid < R) {
+        P.qb->ring[tid].head = 0;
+        P.qb->ring[tid].tail = seeded > tid ? (seeded - tid + R - 1u) / R : 0u;
+        P.qb->ring[tid].signal = 0u;
+    }
     if (tid == 0) {
-        P.q->head = 0;
-        P.q->tail = (uint32_t)P.B;
-        P.q->pending = P.B;
-        P.q->signal = 0u;
-        P.q->produced = 0;
-        P.q->stop = 0;
-        P.q->stop_reason = 0;
+        P.g->pending = (int32_t)seeded;
+        P.g->produced = 0;
+        P.g->stop = 0;
+        P.g->stop_reason = 0;
+        P.g->next_inst = seeded;
     }
 }
 

@@ -42,6 +42,7 @@ class Limits(ctypes.Structure):
         ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("explore_pm", ctypes.c_int32),
         ("trace_buf", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint32),
         ("use_graph", ctypes.c_int32), ("two_way", ctypes.c_int32),
+        ("active_per_xcd", ctypes.c_int32),
     ]
 
 
@@ -119,7 +120,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32),
-                                    ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+                                    ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.cubics_policy_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
     lib.cubics_policy_free.argtypes = [vp]
     lib.cubics_policy_free.restype = None
@@ -129,7 +130,8 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_mlp_grad.argtypes = [vp, vp, i32, vp, i32, i64, vp, vp]
     lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
-              "cubics_root", "cubics_features", "cubics_solve", "cubics_solve_batch", "cubics_autotune", "cubics_policy_create",
+              "cubics_root", "cubics_features", "cubics_solve", "cubics_solve_batch",
+              "cubics_autotune", "cubics_policy_create",
               "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
               "cubics_mlp_train_step"):
         getattr(lib, f).restype = ctypes.c_int
@@ -264,7 +266,8 @@ class Context:
     def autotune(self, probs, mode: int = MODE_COUNT, time_ms: int = 50, rates: bool = False, **kw):
         """cubics_autotune: returns the chosen layout (1 LANE, 2 SEG, 3 VAR);
         with rates=True, (layout, worker divisor, {(layout, divisor): nodes
-        per ms}) for every pair tried."""
+        per ms}) for every pair tried; self.last_active_per_xcd keeps the
+        chosen instances per XCD queue (0 = one queue)."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()
@@ -273,10 +276,13 @@ class Context:
             L.donate = 1 if kw.get("donate", True) else 0
             L.split_target = kw.get("split_target", 0)
             L.max_nodes = kw.get("max_nodes", 0)
+            L.active_per_xcd = kw.get("active_per_xcd", 0)
             lims[b] = L
-        chosen, div = ctypes.c_int32(), ctypes.c_int32()
+        chosen, div, act = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         rt = (ctypes.c_double * (3 * AUTOTUNE_DIVS))()
-        _check(_lib.cubics_autotune(arr, B, mode, lims, time_ms, ctypes.byref(chosen), ctypes.byref(div), rt))
+        _check(_lib.cubics_autotune(arr, B, mode, lims, time_ms, ctypes.byref(chosen), ctypes.byref(div),
+                                    ctypes.byref(act), rt))
+        self.last_active_per_xcd = act.value
         if rates:
             table = {(k // AUTOTUNE_DIVS + 1, AUTOTUNE_DIV_VALUES[k % AUTOTUNE_DIVS]): rt[k]
                      for k in range(3 * AUTOTUNE_DIVS) if rt[k] > 0}
@@ -367,7 +373,7 @@ class Context:
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
                     explore_pm: int = 0, seed: int = 0, use_graph: bool = False,
-                    two_way: bool = False, sol_out=None):
+                    two_way: bool = False, sol_out=None, active_per_xcd: int = 0):
         """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records.
         sol_out: optional int32 cuda tensor [B, >= max n]; FIRST mode stores
         instance b's solution in row b (no per-instance buffers, and the
@@ -392,6 +398,7 @@ class Context:
             if sol_out is not None:
                 L.sol_buf = base + b * row
                 L.sol_capacity = 1
+            L.active_per_xcd = active_per_xcd
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()

@@ -50,6 +50,6 @@ def test_null_arguments_are_rejected_without_gpu_work():
     assert lib.cubics_lns(None, 0, None, None, None, 0, None, None, None, None, None, None, None, None,
                           None, None, None, None) == -1
     lib.cubics_autotune.restype = ctypes.c_int
-    assert lib.cubics_autotune(None, 0, 0, None, ctypes.c_int64(1), None, None, None) == -1
+    assert lib.cubics_autotune(None, 0, 0, None, ctypes.c_int64(1), None, None, None, None) == -1
     lib.cubics_free(None)
     lib.cubics_destroy(None)

@@ -9,6 +9,7 @@
 * the random binary configuration: 13-queens and RB slices against the
   oracle, and slice sums against a full GPU count.
 """
+import os
 import sys
 
 import numpy as np
@@ -113,31 +114,67 @@ def test_batch_count_matches_single(ctx, cb):
     assert resolved >= 8
 
 
+BENCH_BUDGET = 50_000  # node budget per instance of the benchmark's batch
+
+
+def _sweep_golden():
+    rows = _golden_rows("sweep_verdicts.txt")
+    assert len(rows) == 4096
+    out = {}
+    for r in rows:
+        out[int(r[0])] = (r[1], int(r[2]), int(r[3]))
+    return out
+
+
+def _check_batch_against_oracle(insts, res, sols, golden, tag):
+    """Every GPU SAT assignment verified; every instance the oracle resolved
+    within its budget resolved by the GPU with the same verdict; every
+    oracle UNSAT (a whole first-fail tree) with the same node and failure
+    counts.  Returns the number of GPU UNSAT verdicts the oracle left
+    unresolved."""
+    n_sat = n_unsat = unchecked = 0
+    for b, (inst, r) in enumerate(zip(insts, res)):
+        v, nodes, fails = golden[b]
+        if r.verdict == "SAT":
+            n_sat += 1
+            assert oracle.verify(inst, sols[b, :inst.n]), (tag, inst.name)
+        elif r.verdict == "UNSAT":
+            n_unsat += 1
+            unchecked += v == "LIMIT"
+        if v != "LIMIT":
+            assert r.verdict == v, (tag, inst.name, r.verdict, v)
+        if v == "UNSAT":
+            assert (r.nodes, r.fails) == (nodes, fails), (tag, inst.name)
+    _say(f"{tag}: sat={n_sat} unsat={n_unsat} (oracle-unresolved unsat {unchecked}) "
+         f"limit={len(res) - n_sat - n_unsat} kernel_ms={res[0].kernel_ms:.0f}")
+    return unchecked
+
+
 def test_batch_full_size(ctx, cb):
-    """4096 instances, n in [20,120], d in [8,64], in one persistent launch."""
+    """The benchmark's batch: 4096 instances (n in [20,120], d in [8,64])
+    in one persistent launch, find-first, a node budget of 50,000 each,
+    with the autotuned layout, then once more replayed from a hipGraph.
+    Checked on every instance against the oracle's stored verdicts (budget
+    20,000 nodes each, tests/golden/sweep_verdicts.txt)."""
+    import torch
+    golden = _sweep_golden()
     insts = _sweep(4096)
     _say("generated 4096 sweep instances")
     probs = [ctx.load(x) for x in insts]
     _say("loaded")
-    res = ctx.solve_batch(probs, cb.MODE_FIRST, max_nodes=200_000, layout=1)
-    n_sat = n_unsat = 0
-    for inst, r in zip(insts, res):
-        if r.verdict == "SAT":
-            n_sat += 1
-            assert oracle.verify(inst, r.solutions[0]), inst.name
-        elif r.verdict == "UNSAT":
-            n_unsat += 1
-    _say(f"batch: sat={n_sat} unsat={n_unsat} kernel_ms={res[0].kernel_ms:.1f}")
-    assert n_sat + n_unsat > 2048
-    # seeded sample checked against the oracle (budgeted)
-    rng = np.random.default_rng(3)
-    agree = 0
-    for i in rng.choice(4096, 24, replace=False):
-        ref = oracle.solve(insts[i], oracle.MODE_FIRST, max_nodes=20000)
-        if ref.verdict != "LIMIT" and res[i].verdict != "LIMIT":
-            assert ref.verdict == res[i].verdict, insts[i].name
-            agree += 1
-    assert agree >= 8
+    nmax = max(x.n for x in insts)
+    sol = torch.zeros((4096, nmax), dtype=torch.int32, device=ctx.torch_device)
+    chosen = ctx.autotune(probs, cb.MODE_FIRST, time_ms=300, max_nodes=BENCH_BUDGET)
+    _say(f"autotuned layout {chosen}")
+    for tag, kw in (("autotuned", {}), ("graph", {"use_graph": True}), ("graph replay", {"use_graph": True})):
+        sol.zero_()
+        res = ctx.solve_batch(probs, cb.MODE_FIRST, max_nodes=BENCH_BUDGET, sol_out=sol, **kw)
+        s = sol.cpu().numpy()
+        unchecked = _check_batch_against_oracle(insts, res, s, golden, tag)
+        assert unchecked <= 64, unchecked
+    resolved = sum(v != "LIMIT" for v, _, _ in golden.values())
+    _say(f"oracle resolved {resolved} of 4096 within 20,000 nodes")
+    assert resolved >= 2500
 
 
 # ---------------------------------------------------- random binary config
@@ -160,6 +197,54 @@ def test_rb_full_size_sampled_subproblems(ctx, cb):
         ref = oracle.solve(sub, oracle.MODE_COUNT)
         r = ctx.solve(ctx.load(sub), cb.MODE_COUNT)
         assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden_rows(name):
+    """Data rows of a stored oracle result (tests/golden/make_goldens.py)."""
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [line.split() for line in f if line.strip() and not line.startswith("#")]
+
+
+def test_rb_bench_slice_partition(ctx, cb):
+    """The benchmark's RB slice x0 = 1 (n=40, d=16, tightness 0.35): its
+    full GPU count equals the oracle's count summed over the 16 sub-CSPs
+    x1 = v, and every sub-CSP's count, node and failure counts equal the
+    oracle's (stored, tests/golden/rb_slice_x0_1.txt)."""
+    inst = cspgen.rb(0, n=40, d=16, dens_pm=250, tight_pm=350, base=cspgen.SEED_RB)
+    rows = {int(r[0]): tuple(int(x) for x in r[1:]) for r in _golden_rows("rb_slice_x0_1.txt")}
+    assert sorted(rows) == list(range(16))
+    full = ctx.solve(ctx.load(inst.fix({0: 1})), cb.MODE_COUNT)
+    _say(f"RB slice x0=1: {full.count} solutions, {full.nodes} nodes, {full.kernel_ms:.0f} ms")
+    assert full.verdict == "SAT" and full.count == sum(r[0] for r in rows.values())
+    for v in range(16):
+        r = ctx.solve(ctx.load(inst.fix({0: 1, 1: v})), cb.MODE_COUNT)
+        assert (r.count, r.nodes, r.fails) == rows[v], v
+
+
+def test_rb_bench_depth2_subproblems(ctx, cb):
+    """Seeded sub-CSPs of the benchmark's RB instance with x0 and x1 fixed
+    (about 10^9 nodes each): count, node and failure counts equal the
+    oracle's (stored, tests/golden/rb_depth2.txt)."""
+    inst = cspgen.rb(0, n=40, d=16, dens_pm=250, tight_pm=350, base=cspgen.SEED_RB)
+    rows = _golden_rows("rb_depth2.txt")
+    assert len(rows) >= 6
+    for a, b, count, nodes, fails in ([int(x) for x in r] for r in rows):
+        r = ctx.solve(ctx.load(inst.fix({0: a, 1: b})), cb.MODE_COUNT)
+        assert (r.count, r.nodes, r.fails) == (count, nodes, fails), (a, b)
+
+
+def test_rb_tightness_040_full_count(ctx, cb):
+    """RB n=40, d=16 at tightness 0.40 (102 of 256 pairs forbidden per
+    table) counted exhaustively: count, nodes and failures equal the
+    oracle's (stored, tests/golden/rb_tight400.txt)."""
+    inst = cspgen.rb(0, n=40, d=16, dens_pm=250, tight_pm=400, base=cspgen.SEED_RB)
+    want = {r[0]: int(r[1]) for r in _golden_rows("rb_tight400.txt")}
+    for layout in (0, 1, 3):
+        r = ctx.solve(ctx.load(inst), cb.MODE_COUNT, layout=layout)
+        assert (r.count, r.nodes, r.fails) == (want["count"], want["nodes"], want["fails"]), layout
 
 
 def test_rb_slices_sum_to_full_count(ctx, cb):
