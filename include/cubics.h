@@ -245,6 +245,27 @@ int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits *limits,
 int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode,
                        const cubics_limits *limits, cubics_result *results);
 
+/* Allocation-free variant of cubics_solve_batch, for callers that cannot
+   allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid hipMalloc).  Same arguments, semantics and
+   results as cubics_solve_batch, except that every device buffer of the
+   launch (instance descriptors, per-instance counters, the work queue, the
+   workers' trail stacks) comes from a static device array of
+   CUBICS_STATIC_SCRATCH_MIB MiB that each GPU holds from its first use until
+   the process ends; the call allocates no device memory itself (the
+   problems, the context and the caller's solution buffers exist already).
+   The worker count shrinks until the trails fit the array, so a launch may
+   run on fewer workers than cubics_solve_batch would use.  Errors: as
+   cubics_solve_batch, plus EUNSUPPORTED when even one worker does not fit
+   (B descriptors + queue + one trail exceed the array) and EINVAL for
+   use_graph or trace recording, which need allocations.  Every call on one
+   GPU shares that GPU's array and the last call's contents stay in it:
+   calls that overlap on one GPU (other threads, other streams) race and
+   must be serialised by the caller. */
+#define CUBICS_STATIC_SCRATCH_MIB 256
+int cubics_solve_batch_static(cubics_prob *const *probs, int32_t B, int32_t mode,
+                              const cubics_limits *limits, cubics_result *results);
+
 /* Autotuner: run these problems for time_ms of search under each revision
    layout they admit (LANE, SEG, VAR) and each of CUBICS_AUTOTUNE_DIVS worker
    counts (the occupancy-limited maximum divided by 1, 2 and 4: a small

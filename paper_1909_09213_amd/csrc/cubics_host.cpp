@@ -562,6 +562,37 @@ extern "C" int cubics_prob_info(const cubics_prob *p, int32_t *n, int32_t *W, in
 // ------------------------------------------------------------ solve support
 int policy_fill(const cubics_policy *pol, PolicyDev *out);
 
+// ---- static scratch of the allocation-free batch solve
+// The buffers of one cubics_solve_batch_static launch (instance descriptors,
+// per-instance counters, the work queue and the workers' trail stacks) are
+// carved out of this array.  Each GPU the library runs on holds its own copy
+// from the first use until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels and copies get the device
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t CUBICS_STATIC_SCRATCH_BYTES = (size_t)CUBICS_STATIC_SCRATCH_MIB << 20;
+static __device__ __align__(256) uint8_t scratch[CUBICS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on `device` (which must be current),
+// looked up once per device.
+int scratch_address(int device, uint8_t **out) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(CUBICS_EUNSUPPORTED, "device %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CUBICS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = (uint8_t *)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return CUBICS_OK;
+}
+}  // namespace
 
 namespace {
 
@@ -621,8 +652,10 @@ int choose_layout(cubics_prob *const *probs, int B, int requested) {
 // worker_div > 0: use the occupancy-limited worker count divided by it (the
 // autotuner's candidates); 0: the caller's count, else the autotuned one for
 // an AUTO layout, else the maximum.
+// static_scratch: take every device buffer from the static scratch array
+// (no allocation; the worker count shrinks until the launch fits).
 static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_limits *lims,
-                      cubics_result *results, int worker_div = 0) {
+                      cubics_result *results, int worker_div = 0, bool static_scratch = false) {
     auto t0 = std::chrono::steady_clock::now();
     if (!probs || B < 1 || !results) return fail(CUBICS_EINVAL, "bad batch arguments");
     if (mode < 0 || mode > 2) return fail(CUBICS_EINVAL, "bad mode %d", mode);
@@ -733,13 +766,48 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
         while ((long long)c < want) c *= 2;
         return c;
     };
+    const auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    // bytes of the launch's buffers in the static scratch layout
+    const auto static_bytes = [&](int nw_) {
+        const size_t c = (size_t)queue_cells(nw_) * ring_count(nw_);
+        return al(sizeof(InstDev) * (size_t)B) + al(sizeof(InstCtl) * (size_t)B) + al(sizeof(QBlock)) +
+               al(4ull * c) + al(4ull * c * slot_words) + 4ull * trail_words * (size_t)nw_;
+    };
+    if (static_scratch) {
+        if (static_bytes(1) > CUBICS_STATIC_SCRATCH_BYTES)
+            return fail(CUBICS_EUNSUPPORTED, "the launch needs %zu bytes with one worker; the static scratch holds %zu",
+                        static_bytes(1), CUBICS_STATIC_SCRATCH_BYTES);
+        // the most workers whose trails fit (the count only shrinks)
+        int lo_w = 1, hi_w = nworkers;
+        while (lo_w < hi_w) {
+            const int mid = lo_w + (hi_w - lo_w + 1) / 2;
+            if (static_bytes(mid) <= CUBICS_STATIC_SCRATCH_BYTES) lo_w = mid;
+            else hi_w = mid - 1;
+        }
+        nworkers = lo_w;
+    }
     const int blocks = (nworkers + wpb - 1) / wpb;
     const uint32_t cap = queue_cells(nworkers);  // per ring
     const int nrings = ring_count(nworkers);
     const size_t cells = (size_t)cap * nrings;
     void *d_inst, *d_ctl, *d_q, *d_qseq, *d_qdata, *d_trail;
     int rc;
-    {
+    if (static_scratch) {
+        uint8_t *base = nullptr;
+        if ((rc = scratch_address(ctx->device, &base))) return rc;
+        size_t off = 0;
+        const auto take = [&](size_t bytes) {
+            void *p_ = base + off;
+            off += al(bytes);
+            return p_;
+        };
+        d_inst = take(sizeof(InstDev) * (size_t)B);
+        d_ctl = take(sizeof(InstCtl) * (size_t)B);
+        d_q = take(sizeof(QBlock));
+        d_qseq = take(4ull * cells);
+        d_qdata = take(4ull * cells * slot_words);
+        d_trail = take(4ull * trail_words * (size_t)nworkers);
+    } else {
         if ((rc = ctx->inst.ensure(sizeof(InstDev) * (size_t)B))) return rc;
         if ((rc = ctx->ctl.ensure(sizeof(InstCtl) * (size_t)B))) return rc;
         if ((rc = ctx->q.ensure(sizeof(QBlock)))) return rc;
@@ -1000,6 +1068,15 @@ extern "C" int cubics_solve(cubics_prob *prob, int32_t mode, const cubics_limits
 extern "C" int cubics_solve_batch(cubics_prob *const *probs, int32_t B, int32_t mode, const cubics_limits *limits,
                                   cubics_result *results) {
     return solve_impl(probs, B, mode, limits, results);
+}
+
+extern "C" int cubics_solve_batch_static(cubics_prob *const *probs, int32_t B, int32_t mode,
+                                         const cubics_limits *limits, cubics_result *results) {
+    if (limits && limits[0].use_graph)
+        return fail(CUBICS_EINVAL, "cubics_solve_batch_static: use_graph is not available (a graph allocates)");
+    if (limits && (limits[0].trace_buf || limits[0].trace_capacity))
+        return fail(CUBICS_EINVAL, "cubics_solve_batch_static: trace recording is not available");
+    return solve_impl(probs, B, mode, limits, results, 0, true);
 }
 
 extern "C" int cubics_features(cubics_prob *p, const uint32_t *dom_bits, int32_t depth, float *out) {

@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_features.argtypes = [vp, vp, i32, vp]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
+    lib.cubics_solve_batch_static.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), i64, ctypes.POINTER(i32),
                                     ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
     lib.cubics_policy_create.argtypes = [vp, vp, ctypes.POINTER(vp)]
@@ -131,7 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
               "cubics_root", "cubics_features", "cubics_solve", "cubics_solve_batch",
-              "cubics_autotune", "cubics_policy_create",
+              "cubics_solve_batch_static", "cubics_autotune", "cubics_policy_create",
               "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
               "cubics_mlp_train_step"):
         getattr(lib, f).restype = ctypes.c_int
@@ -373,11 +374,14 @@ class Context:
                     layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
                     explore_pm: int = 0, seed: int = 0, use_graph: bool = False,
-                    two_way: bool = False, sol_out=None, active_per_xcd: int = 0):
+                    two_way: bool = False, sol_out=None, static_scratch: bool = False,
+                    active_per_xcd: int = 0):
         """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records.
         sol_out: optional int32 cuda tensor [B, >= max n]; FIRST mode stores
         instance b's solution in row b (no per-instance buffers, and the
-        results carry no solutions: read them from sol_out)."""
+        results carry no solutions: read them from sol_out).
+        static_scratch: call cubics_solve_batch_static (the allocation-free
+        variant) instead of cubics_solve_batch."""
         B = len(probs)
         arr = (ctypes.c_void_p * B)(*[p.handle for p in probs])
         lims = (Limits * B)()
@@ -402,7 +406,8 @@ class Context:
             lims[b] = L
             bufs.append(buf)
         res = (_Result * B)()
-        _check(_lib.cubics_solve_batch(arr, B, mode, lims, res))
+        fn = _lib.cubics_solve_batch_static if static_scratch else _lib.cubics_solve_batch
+        _check(fn(arr, B, mode, lims, res))
         return [self._result(res[b], bufs[b], probs[b].n) for b in range(B)]
 
 
