@@ -165,7 +165,9 @@ def leg_rb(ctx, cb, cspgen):
     names = {1: "lane", 2: "seg", 3: "var"}
     sl = ctx.load(inst.fix({0: 1}))
     r = ctx.solve(sl, cb.MODE_COUNT)
-    q = ctx.solve(ctx.load(cspgen.queens(13)), cb.MODE_COUNT)
+    q13 = ctx.load(cspgen.queens(13))
+    qchosen, qdiv = ctx.autotune([q13], cb.MODE_COUNT, time_ms=100, rates=True)[:2]
+    q = ctx.solve(q13, cb.MODE_COUNT)
     assert q.count == 73712, q.count
     return {"workload": "model-RB n=40 d=16 density 0.25 tightness 0.35 (seed 2 index 0), "
                         "slice x0=1 count-all; 13-queens count-all",
@@ -175,6 +177,7 @@ def leg_rb(ctx, cb, cspgen):
             "slice_revisions_per_s": r.revisions / (r.kernel_ms * 1e-3),
             "slice_alg_GBps": r.alg_bytes / (r.kernel_ms * 1e-3) / 1e9,
             "queens13_count": q.count, "queens13_nodes": q.nodes,
+            "queens13_layout": names[qchosen], "queens13_worker_divisor": qdiv,
             "queens13_kernel_ms": round(q.kernel_ms, 3)}
 
 

@@ -205,6 +205,26 @@ struct Counters {
 
 // ------------------------------------------------- binary unit revisions
 
+// Element i of a read-only instance array.  GM: the array lies in global
+// memory (instance tables read from HBM), so the load is a global load with
+// a uniform base and a 32-bit offset; else it may lie in LDS (an instance
+// staged once per workgroup) and goes through a generic pointer.
+template <bool GM, class T>
+DEV T ldg(const T *p, uint32_t i) {
+    if constexpr (GM) return ((const __attribute__((address_space(1))) T *)p)[i];
+    else return p[i];
+}
+template <bool GM>
+DEV Unit ld_unit(const Unit *p, uint32_t i) {
+    if constexpr (GM) {
+        typedef int v4i __attribute__((ext_vector_type(4)));
+        const v4i v = ((const __attribute__((address_space(1))) v4i *)p)[i];
+        return Unit{v.x, v.y, v.z, v.w};
+    } else {
+        return p[i];
+    }
+}
+
 // Rows fetched together by one lane of a LANE table revision: the lane
 // gathers up to RB live values, then issues all their row loads before it
 // uses any, so a revision waits on ceil(|D| / RB) memory round trips instead
@@ -222,11 +242,15 @@ DEV void next_values(uint32_t &bits, int w, int (&ix)[RB]) {
 }
 
 // LANE layout: full new target words for one unit.  A table revision reads
-// min(|D_src|, |D_tgt|) rows: the union of the source values' rows (bits over
-// the target) when the source is the smaller domain, else one row per live
-// target value (bits over the source), tested against the source domain.
-// *rows_read receives that count (the algorithmic row traffic).
-template <int WM>
+// at most min(|D_src|, |D_tgt|) rows: the union of the source values' rows
+// (bits over the target) when the source is the smaller domain - stopping
+// as soon as the union covers every target value, when the rest of the rows
+// cannot remove anything - else one row per live target value (bits over
+// the source), tested against the source domain.  *rows_read receives the
+// rows read (the algorithmic row traffic).  Rows are addressed as 32-bit
+// word offsets from the instance's row section (a uniform base), so that a
+// load needs one address instruction.
+template <int WM, bool GM>
 DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                      const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W, int *rows_read) {
     const int ty = u.tt >> 24;
@@ -235,15 +259,17 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
     *rows_read = 0;
     if (ty == U_TABLE) {
         const int ps = pop_w(ds, W), pt = pop_w(dt, W);
+        const uint32_t Wu = (uint32_t)W;
         if (ps <= pt) {
-            *rows_read = ps;
             uint32_t acc[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) acc[k] = 0u;
-            const uint32_t *rows = I.rows + u.p1;
+            const uint32_t base = (uint32_t)u.p1;
+            int nread = 0;
+            bool covered = false;
 #pragma unroll
             for (int w = 0; w < WM; ++w) {
-                if (w >= W) break;
+                if (w >= W || covered) break;
                 uint32_t bits = ds[w];
                 while (bits) {
                     int ix[RB];
@@ -252,13 +278,23 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
-                        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? rows[(ptrdiff_t)ix[q] * W + k] : 0u;
+                        for (int k = 0; k < WM; ++k)
+                            r[q][k] = k < W ? ldg<GM>(I.rows, base + (uint32_t)ix[q] * Wu + (uint32_t)k) : 0u;
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
                         for (int k = 0; k < WM; ++k) acc[k] |= r[q][k];
+                    nread += RB;
+                    uint32_t open = 0u;
+#pragma unroll
+                    for (int k = 0; k < WM; ++k) open |= dt[k] & ~acc[k];
+                    if (open == 0u) {
+                        covered = true;
+                        break;
+                    }
                 }
             }
+            *rows_read = min(nread, ps);
 #pragma unroll
             for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
         } else {
@@ -266,7 +302,7 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
             uint32_t keep[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) keep[k] = 0u;
-            const uint32_t *rows = I.rows + u.p0;
+            const uint32_t base = (uint32_t)u.p0;
 #pragma unroll
             for (int w = 0; w < WM; ++w) {
                 if (w >= W) break;
@@ -278,7 +314,8 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
-                        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? rows[(ptrdiff_t)ix[q] * W + k] : 0u;
+                        for (int k = 0; k < WM; ++k)
+                            r[q][k] = k < W ? ldg<GM>(I.rows, base + (uint32_t)ix[q] * Wu + (uint32_t)k) : 0u;
 #pragma unroll
                     for (int q = 0; q < RB; ++q) {
                         uint32_t hit = 0u;
@@ -332,15 +369,15 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 }
 
 // SEG layout: is target value index a supported by the source domain?
-template <int WM>
+template <int WM, bool GM>
 DEV bool supported_seg(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM], int a, int W) {
     const int ty = u.tt >> 24;
     if (ty == U_TABLE) {
-        const uint32_t *r = I.rows + u.p0 + (size_t)a * W;
+        const uint32_t r0 = (uint32_t)u.p0 + (uint32_t)a * (uint32_t)W;
         uint32_t acc = 0;
 #pragma unroll
         for (int k = 0; k < WM; ++k)
-            if (k < W) acc |= r[k] & ds[k];
+            if (k < W) acc |= ldg<GM>(I.rows, r0 + (uint32_t)k) & ds[k];
         return acc != 0;
     } else if (ty == U_NEQ) {
         return !(pop_w(ds, W) == 1 && low_w(ds, W) + u.p0 == a);
@@ -378,13 +415,13 @@ struct Lds {
 };
 
 // Process one chunk of binary units in LANE layout.  Returns wave-uniform fail.
-template <int WM>
+template <int WM, bool GM>
 DEV bool chunk_lane(const InstDev &I, const Lds &L, u64 *nxt, int my_u, Counters &C, int lane) {
     const int W = I.W;
     bool changed = false;
     int tgt = 0;
     if (my_u >= 0) {
-        const Unit u = I.units[my_u];
+        const Unit u = ld_unit<GM>(I.units, (uint32_t)my_u);
         tgt = u.tt & 0xFFFFFF;
         uint32_t ds[WM], dt[WM], nw[WM];
 #pragma unroll
@@ -393,7 +430,7 @@ DEV bool chunk_lane(const InstDev &I, const Lds &L, u64 *nxt, int my_u, Counters
             dt[k] = k < W ? L.dom[tgt * W + k] : 0u;
         }
         int rows_read = 0;
-        revise_lane<WM>(I, u, ds, dt, nw, W, &rows_read);
+        revise_lane<WM, GM>(I, u, ds, dt, nw, W, &rows_read);
 #pragma unroll
         for (int k = 0; k < WM; ++k) changed |= (k < W) && nw[k] != dt[k];
         C.rev += 1;
@@ -418,7 +455,7 @@ DEV bool chunk_lane(const InstDev &I, const Lds &L, u64 *nxt, int my_u, Counters
 }
 
 // Process one chunk of binary units in SEG layout (W <= 2, S lanes per unit).
-template <int WM>
+template <int WM, bool GM>
 DEV bool chunk_seg(const InstDev &I, const Lds &L, u64 *nxt, int my_u, int sh, Counters &C, int lane) {
     const int W = I.W;
     const int S = 1 << sh;
@@ -429,7 +466,7 @@ DEV bool chunk_seg(const InstDev &I, const Lds &L, u64 *nxt, int my_u, int sh, C
 #pragma unroll
     for (int k = 0; k < WM; ++k) dt[k] = 0u;
     if (my_u >= 0) {
-        u = I.units[my_u];
+        u = ld_unit<GM>(I.units, (uint32_t)my_u);
         const int tgt = u.tt & 0xFFFFFF;
         uint32_t ds[WM];
 #pragma unroll
@@ -438,7 +475,7 @@ DEV bool chunk_seg(const InstDev &I, const Lds &L, u64 *nxt, int my_u, int sh, C
             dt[k] = k < W ? L.dom[tgt * W + k] : 0u;
         }
         const bool live = (a < 32 * W) && ((dt[a >> 5] >> (a & 31)) & 1u);
-        if (live) sup = supported_seg<WM>(I, u, ds, a, W);
+        if (live) sup = supported_seg<WM, GM>(I, u, ds, a, W);
     }
     const u64 m = __ballot(sup);
     bool changed = false;
@@ -850,7 +887,7 @@ DEV bool revise_linear(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt,
 // Revise to the fixpoint.  L.dA holds the initially dirty variables.
 // Returns true on failure (wave-uniform).
 // GLOB: global constraints may occur; SEGC: the SEG layout is compiled in.
-template <int WM, bool GLOB, bool SEGC>
+template <int WM, bool GLOB, bool SEGC, bool GM>
 DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int lane) {
     const int n = I.n;
     const int ndw = (n + 63) >> 6, ngw = (I.n_glob + 63) >> 6;
@@ -870,16 +907,16 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
             while (bits && !fail) {
                 const int j = w * 64 + __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                int beg = I.trig_off[j];
-                const int end = I.trig_off[j + 1];
+                int beg = ldg<GM>(I.trig_off, (uint32_t)j);
+                const int end = ldg<GM>(I.trig_off, (uint32_t)j + 1u);
                 while (beg < end) {
                     const int take = min(end - beg, CH - cnt);
                     if (slot >= cnt && slot < cnt + take) my_u = beg + slot - cnt;
                     cnt += take;
                     beg += take;
                     if (cnt == CH) {
-                        fail = (SEGC && seg) ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
-                                             : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+                        fail = (SEGC && seg) ? chunk_seg<WM, GM>(I, L, nxt, my_u, sh, C, lane)
+                                             : chunk_lane<WM, GM>(I, L, nxt, my_u, C, lane);
                         cnt = 0;
                         my_u = -1;
                         if (fail) break;
@@ -895,8 +932,8 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
             }
         }
         if (!fail && cnt > 0)
-            fail = (SEGC && seg) ? chunk_seg<WM>(I, L, nxt, my_u, sh, C, lane)
-                                 : chunk_lane<WM>(I, L, nxt, my_u, C, lane);
+            fail = (SEGC && seg) ? chunk_seg<WM, GM>(I, L, nxt, my_u, sh, C, lane)
+                                 : chunk_lane<WM, GM>(I, L, nxt, my_u, C, lane);
         if (fail) return true;
         if (GLOB && I.n_glob) {
             wsync();
@@ -1299,7 +1336,7 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
 // Run one task to completion.  FEAT: 0 plain first-fail, 1 learned policy,
 // 2 trace recording (each compiled separately to keep the plain kernel's
 // register budget).
-template <int WM, int FEAT, bool GLOB, bool SEGC>
+template <int WM, int FEAT, bool GLOB, bool SEGC, bool GM>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
                   long long t_start, const PolicyDev &LP) {
@@ -1342,7 +1379,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         int st = node_test<WM>(I, L, lane, &bx);
         if (st == 2) { C.fails += 1; return; }
         dirty_all(L, n, lane);
-        if (propagate<WM, GLOB, SEGC>(I, L, layout, C, lane)) { C.fails += 1; return; }
+        if (propagate<WM, GLOB, SEGC, GM>(I, L, layout, C, lane)) { C.fails += 1; return; }
         st = node_test<WM>(I, L, lane, &bx);
         if (st == 1) { record_solution<WM>(P, I, ctl, L, C, lane); return; }
         have_open = true;
@@ -1566,7 +1603,7 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
         C.nodes += 1;
         C.stamp += 1;
         {
-            const bool failed = propagate<WM, GLOB, SEGC>(I, L, layout, C, lane);
+            const bool failed = propagate<WM, GLOB, SEGC, GM>(I, L, layout, C, lane);
             if (failed) {
                 C.fails += 1;
                 if ((tracing || learned) && lane == 0) L.fails[F.x] += 1u;
@@ -2126,7 +2163,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
 template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC, bool VAR = false>
-__global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
+__global__ __launch_bounds__(512, 4) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     // idle_token: 1 while one idle wave of this workgroup polls the global
     // queue; drained: set once that wave saw no task pending anywhere
@@ -2306,7 +2343,7 @@ __global__ __launch_bounds__(512) void search_kernel(SearchParams P) {
             if (VAR)
                 run_task_var<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
             else
-                run_task<WM, FEAT, GLOB, SEGC>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start, LP);
+                run_task<WM, FEAT, GLOB, SEGC, !TL>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start, LP);
         }
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
@@ -2425,7 +2462,7 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
     bool fail = node_test<WM>(I, L, lane, &bx) == 2;
     if (!fail) {
         dirty_all(L, n, lane);
-        fail = propagate<WM, true, true>(I, L, P.layout, C, lane);
+        fail = propagate<WM, true, true, true>(I, L, P.layout, C, lane);
     }
     wsync();
     for (int t = lane; t < nw; t += 64) out[t] = L.dom[t];
