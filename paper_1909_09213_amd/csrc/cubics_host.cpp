@@ -620,7 +620,8 @@ Geometry geometry(cubics_prob *const *probs, int B) {
     g.wmax = wm <= 1 ? 1 : wm <= 2 ? 2 : wm <= 4 ? 4 : 8;
     const int ndw = (g.nmax + 63) / 64, ngw = std::max((g.gmax + 63) / 64, 1);
     int words = ((g.nmax * g.wmax) + 1) & ~1;
-    words += 2 * ndw + 2 * ndw + 2 * ngw + ((g.nmax + 1) & ~1) + (g.gac ? SCRATCH_GAC_WORDS : SCRATCH_WORDS);
+    words += 2 * ndw + 2 * ndw + 2 * ngw + ((g.nmax + 1) & ~1) + ((g.nmax + 2) & ~1) +
+             (g.gac ? SCRATCH_GAC_WORDS : SCRATCH_WORDS);
     g.lds_words = (words + 1) & ~1;
     return g;
 }

@@ -228,14 +228,16 @@ DEV Unit ld_unit(const Unit *p, uint32_t i) {
 // Rows fetched together by one lane of a LANE table revision: the lane
 // gathers up to RB live values, then issues all their row loads before it
 // uses any, so a revision waits on ceil(|D| / RB) memory round trips instead
-// of |D|.  A missing value reads row -1, the W zero words the packer puts
+// of |D|.  RB * WM <= 16 words are in flight per lane (wider rows, fewer of
+// them).  A missing value reads row -1, the W zero words the packer puts
 // before every row block.
-constexpr int RB = 8;
+template <int WM>
+constexpr int row_batch() { return WM <= 2 ? 8 : (WM == 4 ? 4 : 2); }
 
 template <int WM>
-DEV void next_values(uint32_t &bits, int w, int (&ix)[RB]) {
+DEV void next_values(uint32_t &bits, int w, int (&ix)[row_batch<WM>()]) {
 #pragma unroll
-    for (int q = 0; q < RB; ++q) {
+    for (int q = 0; q < row_batch<WM>(); ++q) {
         ix[q] = bits ? 32 * w + __ffs(bits) - 1 : -1;
         bits &= bits - 1u;
     }
@@ -254,6 +256,7 @@ template <int WM, bool GM>
 DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                      const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W, int *rows_read) {
     const int ty = u.tt >> 24;
+    constexpr int RB = row_batch<WM>();
 #pragma unroll
     for (int k = 0; k < WM; ++k) nw[k] = dt[k];
     *rows_read = 0;
@@ -410,6 +413,8 @@ struct Lds {
     u64 *dA, *dB;    // dirty sets [ndw]
     u64 *gp;         // pending globals [ngw]
     uint32_t *fails; // [nmax] failures below each branching variable (policy feature)
+    int32_t *trig;   // [nmax + 1] the task's instance's unit ranges per source variable
+                     // (staged per task: the fixpoint loop reads two per dirty variable)
     uint32_t *scr;   // 32 words scratch
     float *feat;     // [nmax][4] learned search: the task's static features
 };
@@ -907,8 +912,8 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
             while (bits && !fail) {
                 const int j = w * 64 + __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                int beg = ldg<GM>(I.trig_off, (uint32_t)j);
-                const int end = ldg<GM>(I.trig_off, (uint32_t)j + 1u);
+                int beg = uni(L.trig[j]);
+                const int end = uni(L.trig[j + 1]);
                 while (beg < end) {
                     const int take = min(end - beg, CH - cnt);
                     if (slot >= cnt && slot < cnt + take) my_u = beg + slot - cnt;
@@ -2163,7 +2168,7 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
 template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC, bool VAR = false>
-__global__ __launch_bounds__(512, 4) void search_kernel(SearchParams P) {
+__global__ __launch_bounds__(512, WM <= 2 ? 4 : 1) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     // idle_token: 1 while one idle wave of this workgroup polls the global
     // queue; drained: set once that wave saw no task pending anywhere
@@ -2225,6 +2230,8 @@ __global__ __launch_bounds__(512, 4) void search_kernel(SearchParams P) {
     off += 2 * (ngw > 0 ? ngw : 1);
     L.fails = base + off;
     off += (P.nmax + 1) & ~1;
+    L.trig = (int32_t *)(base + off);
+    off += (P.nmax + 2) & ~1;
     L.feat = nullptr;
     if (FEAT == 1) {  // the learned search's copy of the task's static features
         L.feat = (float *)(base + off);
@@ -2330,6 +2337,8 @@ __global__ __launch_bounds__(512, 4) void search_kernel(SearchParams P) {
         } else {
             for (int t = lane; t < nw; t += 64) L.dom[t] = ld_rlx(s + SLOT_HDR + t);
         }
+        if (!VAR)
+            for (int t = lane; t <= I.n; t += 64) L.trig[t] = I.trig_off[t];
         wsync();
         // the slot's words are in LDS now: hand the cell back to producers
         if (s && lane == 0) st_rlx(&P.qseq[cell], pos + P.qmask + 1u);
@@ -2447,10 +2456,13 @@ __global__ void root_kernel(SearchParams P, uint32_t *out, int32_t *failed, unsi
     off += 2 * (ngw > 0 ? ngw : 1);
     L.fails = lds_raw + off;
     off += (P.nmax + 1) & ~1;
+    L.trig = (int32_t *)(lds_raw + off);
+    off += (P.nmax + 2) & ~1;
     L.scr = lds_raw + off;
     L.feat = nullptr;
     const int n = I.n, W = I.W, nw = n * W;
     for (int t = lane; t < nw; t += 64) L.dom[t] = I.dom0[t];
+    for (int t = lane; t <= n; t += 64) L.trig[t] = I.trig_off[t];
     wsync();
     for (int t = lane; t < I.n_unary; t += 64) {
         const int v = I.unary[2 * t], o = I.unary[2 * t + 1];
