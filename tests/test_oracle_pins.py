@@ -268,6 +268,43 @@ def test_sum_le_closed_form(n, U, b):
     assert all(Di == list(range(min(U, b) + 1)) for Di in D)
 
 
+def _sum_le_tree_nodes(n, U, b):
+    """Nodes of the first-fail d-way tree of sum x_i <= b over {0..U}^n under
+    bounds reasoning, counted from the structure of the problem alone.
+    Bounds reasoning is exact for one sum of non-negative variables: after
+    labelling x_1..x_j with sum S every unlabelled domain is {0..min(U, b-S)}
+    and every such value extends to a solution, so no node fails.  All
+    unlabelled domains stay equal, so first-fail labels x_1, x_2, ... in
+    index order, and a node branches unless its unlabelled domains are all
+    singletons, i.e. unless S = b (or U = 0, or every variable is labelled).
+    Level j therefore holds the prefixes (x_1..x_j) with sum <= b whose
+    first j-1 values sum to less than b; counted by dynamic programming over
+    the prefix sum.  (Propagation weaker than bounds consistency would fail
+    on some children; none can be stronger.)"""
+    if U == 0:
+        return 1
+    nodes = 1
+    ways = {0: 1}  # prefix sum -> prefixes of the current level that branch
+    for j in range(1, n + 1):
+        nxt = {}
+        for S, w in ways.items():
+            if S >= b:
+                continue  # all unlabelled domains are {0}: a leaf
+            for v in range(0, min(U, b - S) + 1):
+                nxt[S + v] = nxt.get(S + v, 0) + w
+        nodes += sum(nxt.values())
+        ways = nxt
+    return nodes
+
+
+@pytest.mark.parametrize("n,U,b", [(3, 4, 5), (4, 3, 7), (5, 2, 4), (2, 9, 12), (6, 1, 3), (4, 5, 30)])
+def test_sum_le_node_count_closed_form(n, U, b):
+    inst = _custom(n, [0] * n, [U + 1] * n, [(6, tuple(range(n)), (b,) + (1,) * n, ())])
+    r = oracle.solve(inst, oracle.MODE_COUNT)
+    assert r.fails == 0
+    assert r.nodes == _sum_le_tree_nodes(n, U, b)
+
+
 def _knapsack_count(coef, U, b):
     # number of x in prod {0..U_t} with sum coef_t x_t <= b, by DP over the sum
     ways = {0: 1}
