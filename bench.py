@@ -327,12 +327,15 @@ def main():
             # time-to-all-solutions, learned vs first-fail (same GPU, same
             # layout and launch for both policies)
             from paper_1909_09213_amd import learn
-            say("leg learned_vs_first_fail")
-            t = time.perf_counter()
-            rep = learn.experiment(ctx, n_train=args.learned_train, n_eval=args.learned_eval)
-            rep.pop("theta")
-            rep["seconds_total"] = round(time.perf_counter() - t, 2)
-            out["learned_vs_first_fail"] = rep
+            out["learned_vs_first_fail"] = {}
+            for fam in ("sweep", "global"):
+                say(f"leg learned_vs_first_fail ({fam})")
+                t = time.perf_counter()
+                rep = learn.experiment(ctx, n_train=args.learned_train, n_eval=args.learned_eval,
+                                       family=fam)
+                rep.pop("theta")
+                rep["seconds_total"] = round(time.perf_counter() - t, 2)
+                out["learned_vs_first_fail"][fam] = rep
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

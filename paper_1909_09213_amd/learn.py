@@ -64,6 +64,25 @@ def instances(base: int, count: int, **ranges):
     return [cspgen.rb_sweep(i, base=base, **r) for i in range(count)]
 
 
+def global_instances(base: int, count: int):
+    """The learned-branching workload of the all-different + linear family,
+    at sizes whose trees can be counted exhaustively: per instance n in
+    {8, 9} variables over 0..d-1 with d in {6, 7, 8} (drawn from the
+    instance seed), two all-different constraints over ceil(n/2) variables
+    each and three linear <= constraints over all variables, b = 45% of the
+    largest sum (the full family's rules)."""
+    out = []
+    for i in range(count):
+        r = int(cspgen.rng_below(cspgen.instance_seed(base, i), 6, 1)[0])
+        n, d = 8 + r // 3, 6 + r % 3
+        out.append(cspgen.global_family(i, n=n, lo=0, d=d, n_ad=2, k_ad=(n + 1) // 2, n_lin=3, lin_k=0,
+                                        amax=9, b_pm=450, base=base))
+    return out
+
+
+FAMILIES = {"sweep": instances, "global": global_instances}
+
+
 def collect(ctx: cb.Context, insts, cap: int = 4_000_000, explore_pm: int = 250, seed: int = 1,
             chunk: int = 2048, max_nodes: int = 2_000_000):
     """Trace records [N, 8] (torch float32 on the device)."""
@@ -282,14 +301,18 @@ def evaluate(ctx: cb.Context, insts, policy, mode: int = cb.MODE_COUNT, max_node
 
 def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps: int = 1500,
                lr: float = 1e-2, eval_max_nodes: int = 50_000_000,
-               train_base: int = cspgen.SEED_TRAIN, eval_base: int = cspgen.SEED_EVAL):
-    """Sample one node from each of n_train seeded instances, label the
-    alternative branchings there with the plain solver's subtree sizes,
+               train_base: int = cspgen.SEED_TRAIN, eval_base: int = cspgen.SEED_EVAL,
+               family: str = "sweep"):
+    """Sample one node from each of n_train seeded instances of `family`
+    ("sweep": the batched random binary generator at reduced sizes;
+    "global": the all-different + linear generator at reduced sizes), label
+    the alternative branchings there with the plain solver's subtree sizes,
     train, and evaluate time-to-all (count mode) on n_eval held-out seeds
     under first-fail and the policy.  Returns a report dict; raises if any
     verdict or count differs."""
+    make = FAMILIES[family]
     t0 = time.perf_counter()
-    train_insts = instances(train_base, n_train)
+    train_insts = make(train_base, n_train)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     nodes = sample_nodes(ctx, train_insts, seed=train_base)
@@ -299,7 +322,7 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
     t0 = time.perf_counter()
     pol, losses = train(ctx, rec, steps=steps, lr=lr)
     t_train = time.perf_counter() - t0
-    eval_insts = instances(eval_base, n_eval)
+    eval_insts = make(eval_base, n_eval)
     ev = evaluate(ctx, eval_insts, pol, cb.MODE_COUNT, max_nodes=eval_max_nodes)
     ff, le = ev["first_fail"]["results"], ev["learned"]["results"]
     both = [i for i in range(n_eval) if ff[i].verdict != "LIMIT" and le[i].verdict != "LIMIT"]
@@ -309,8 +332,11 @@ def experiment(ctx: cb.Context, n_train: int = 20000, n_eval: int = 4096, steps:
     nodes_ff = sum(ff[i].nodes for i in both)
     nodes_le = sum(le[i].nodes for i in both)
     ratios = np.array([le[i].nodes / ff[i].nodes for i in both], dtype=np.float64)
+    c7 = centre_labels(rec)[:, 7].double()
     report = {
+        "family": family,
         "train_instances": n_train, "train_nodes": len(nodes), "eval_instances": n_eval,
+        "label_variance": float((c7 * c7).mean().item()) if c7.numel() else None,
         "eval_resolved_by_both": len(both),
         "records": int(rec.shape[0]), "train_steps": steps,
         "loss_first": losses[0], "loss_last": losses[-1],

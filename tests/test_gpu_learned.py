@@ -208,6 +208,11 @@ def test_trained_policy_gains_over_first_fail(ctx, cb):
     nodes = learn.sample_nodes(ctx, train, seed=1)
     rec = learn.sibling_records(ctx, train, nodes, seed=1)
     pol, losses = learn.train(ctx, rec, steps=800, lr=1e-2)
+    # the network explains a real part of the centred labels' variance (the
+    # loss of the best constant predictor)
+    c = learn.centre_labels(rec)[:, 7].double()
+    var0 = float((c * c).mean().item())
+    assert losses[-1] < 0.8 * var0, (losses[-1], var0)
     held = learn.instances(cspgen.SEED_EVAL, 256)
     ev = learn.evaluate(ctx, held, pol, cb.MODE_COUNT, max_nodes=20_000_000)
     ff, le = ev["first_fail"]["results"], ev["learned"]["results"]
@@ -222,3 +227,29 @@ def test_trained_policy_gains_over_first_fail(ctx, cb):
           f"{ev['first_fail']['kernel_ms']:.0f} -> {ev['learned']['kernel_ms']:.0f}", file=sys.stderr)
     assert geo < 0.9
     assert (r < 1).sum() > 2 * (r > 1).sum()
+
+
+def test_global_family_policy_keeps_counts(ctx, cb):
+    """The all-different + linear family at countable sizes: a policy
+    trained on sibling subtree sizes of 300 instances counts 128 held-out
+    instances exactly as first-fail does (same counts and verdicts; node
+    counts may differ)."""
+    from paper_1909_09213_amd import learn
+    train = learn.global_instances(cspgen.SEED_TRAIN + 1000, 300)
+    nodes = learn.sample_nodes(ctx, train, seed=2)
+    rec = learn.sibling_records(ctx, train, nodes, seed=2)
+    assert rec.shape[0] > 500
+    pol, losses = learn.train(ctx, rec, steps=400, lr=1e-2)
+    assert losses[-1] < losses[0]
+    held = learn.global_instances(cspgen.SEED_EVAL + 1000, 128)
+    ev = learn.evaluate(ctx, held, pol, cb.MODE_COUNT, max_nodes=20_000_000)
+    ff, le = ev["first_fail"]["results"], ev["learned"]["results"]
+    both = [i for i in range(len(held)) if ff[i].verdict != "LIMIT" and le[i].verdict != "LIMIT"]
+    assert len(both) == len(held)
+    for i in both:
+        assert (ff[i].count, ff[i].verdict) == (le[i].count, le[i].verdict), held[i].name
+    for i in range(0, len(held), 16):
+        ref = oracle.solve(held[i], oracle.MODE_COUNT)
+        assert ff[i].count == ref.count, held[i].name
+    r = np.array([le[i].nodes / ff[i].nodes for i in both])
+    print(f"global family: node ratio geomean {float(np.exp(np.mean(np.log(r)))):.3f}", file=sys.stderr)
