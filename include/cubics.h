@@ -143,6 +143,15 @@ typedef struct {
                                 -1 = every instance queued at launch on one queue;
                                 0 = the autotuned choice for the batch's shape (layout
                                 AUTO), else one queue */
+    const cubics_policy *value_policy; /* NULL = children of a branching in ascending value
+                                order; else the learned value order: the children of every
+                                d-way branching on x are tried in descending order of
+                                this network's score of each value's features (see
+                                cubics_value_features), lowest value on ties.  Changes which
+                                solution is found first, never the solution set, counts or
+                                (all/count mode) node counts.  Domains of at most 64 values,
+                                d-way only (EINVAL with two_way or trace recording);
+                                runs in the LANE layout */
 } cubics_limits;
 
 typedef struct {
@@ -344,6 +353,16 @@ int cubics_lns(cubics_ctx *ctx, int32_t n, const int32_t *lo, const int32_t *dsi
    log2(1 + failures) = 0.  out (host, n * 5 floats) receives them, row i =
    variable i.  The values are those the branching step computes. */
 int cubics_features(cubics_prob *prob, const uint32_t *dom_bits, int32_t depth, float *out);
+
+/* The 5 value features of every value a < 32 W of variable x at a search
+   node whose domains are dom_bits (host, n * W words; NULL = the initial
+   domains) at the given depth: out (host, 32 W * 5 floats), row a =
+   a / d_x, the mean and the smallest, over x's table constraints, of the
+   fraction of the other variable's current values that x = lo_x + a
+   supports (1 when x has no table constraint), depth / n, |D_x| / d_x;
+   zeros for values not in D_x.  The values the learned value order
+   computes.  EUNSUPPORTED for domains wider than 64 values. */
+int cubics_value_features(cubics_prob *prob, const uint32_t *dom_bits, int32_t depth, int32_t x, float *out);
 
 /* Upload theta (copied) and zero the optimizer state. */
 int cubics_policy_create(cubics_ctx *ctx, const float *theta, cubics_policy **out);

@@ -27,6 +27,8 @@ hipError_t launch_root(int wmax, const SearchParams &P, uint32_t *out, int32_t *
 hipError_t launch_init(const SearchParams &P, hipStream_t st);
 hipError_t launch_features(const InstDev *inst, const uint32_t *dom, int depth, float *out, int n,
                            hipStream_t st);
+hipError_t launch_value_features(const InstDev *inst, const uint32_t *dom, int depth, int x, float *out,
+                                 hipStream_t st);
 hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant);
 }  // namespace cubics
 
@@ -669,6 +671,10 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     memset(&dflt, 0, sizeof dflt);
     dflt.donate = 1;
     const cubics_limits &L0 = lims ? lims[0] : dflt;
+    if (L0.value_policy && L0.two_way)
+        return fail(CUBICS_EINVAL, "a learned value order applies to d-way branching (two_way = 0)");
+    if (L0.value_policy && (L0.trace_buf || L0.trace_capacity))
+        return fail(CUBICS_EINVAL, "a learned value order cannot be combined with trace recording");
     if (L0.branching == CUBICS_BRANCH_LEARNED && !L0.policy)
         return fail(CUBICS_EINVAL, "LEARNED branching needs a policy");
     if (L0.two_way != 0 && L0.two_way != 1) return fail(CUBICS_EINVAL, "two_way must be 0 or 1");
@@ -703,7 +709,12 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     // instance whose packed tables fit is staged in LDS once per workgroup;
     // the register-resident VAR path uses 8 workers per workgroup to share it.
     const size_t LDS_WG_MAX = (size_t)ctx->lds_max - 256;  // the kernel keeps a few static words
-    const int feat = (L0.trace_buf && L0.trace_capacity > 0) ? 2 : (L0.branching == CUBICS_BRANCH_LEARNED ? 1 : 0);
+    const bool vorder = L0.value_policy != nullptr;
+    if (vorder && G.wmax > 2)
+        return fail(CUBICS_EUNSUPPORTED, "a learned value order needs domains of at most 64 values");
+    const int feat = (L0.trace_buf && L0.trace_capacity > 0)
+                         ? 2
+                         : ((L0.branching == CUBICS_BRANCH_LEARNED || vorder) ? 1 : 0);
     bool var_all = G.wmax == 1;
     for (int b = 0; b < B && var_all; ++b) var_all = probs[b]->dev.var_ok != 0;
     // (the VAR layout keeps the frames' meta in lane registers: 64 frames)
@@ -712,9 +723,9 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     int wpb = use_var ? 8 : 4;
     // learned search: each worker also keeps its task's static features [n][4]
     // (placed before the scratch words, which stay last)
-    const int lds_words = G.lds_words + (feat == 1 ? 4 * G.nmax : 0);
+    const int lds_words = G.lds_words + (feat == 1 ? 4 * G.nmax + (vorder ? VALUE_LDS_WORDS : 0) : 0);
     const size_t per_wave = (size_t)lds_words * 4;
-    const size_t pol_bytes = feat == 1 ? (size_t)POLICY_LDS_WORDS * 4 : 0;  // network copy
+    const size_t pol_bytes = feat == 1 ? 2 * (size_t)POLICY_LDS_WORDS * 4 : 0;  // network copies
     const size_t tab_bytes = (B == 1) ? (size_t)probs[0]->dev.blob_words * 4 : 0;
     bool tl = B == 1 && L0.tables_in_lds != 2 && tab_bytes + pol_bytes + per_wave <= LDS_WG_MAX;
     size_t lds = (tl ? tab_bytes : 0) + pol_bytes + per_wave * wpb;
@@ -743,7 +754,9 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     int nworkers = L0.workers > 0 && worker_div == 0 ? L0.workers : std::max(1, bpc * wpb * ctx->cu_count / div);
 
     // ---- buffers
-    const uint32_t frame_words = (uint32_t)((FRAME_HDR + G.nmax * G.wmax + 15) / 16 * 16);
+    // a frame under the learned value order also keeps its values' score keys
+    const uint32_t frame_words =
+        (uint32_t)((FRAME_HDR + G.nmax * G.wmax + 15) / 16 * 16) + (vorder ? FRAME_SCORES : 0);
     const uint32_t slot_words = (uint32_t)((SLOT_HDR + G.nmax * G.wmax + 15) / 16 * 16);
     const int64_t trail_words64 = (int64_t)frame_words * frames;
     if (trail_words64 > (1LL << 28))
@@ -867,6 +880,10 @@ static int solve_impl(cubics_prob *const *probs, int B, int mode, const cubics_l
     P.wmax = G.wmax;
     P.gmax = G.gmax;
     if (L0.policy) policy_fill(L0.policy, &P.policy);
+    if (vorder) {
+        policy_fill(L0.value_policy, &P.vpolicy);
+        P.value_order = 1;
+    }
     if (L0.trace_buf && L0.trace_capacity > 0) {
         if ((rc = ctx->tracecnt.ensure(64))) return rc;
         P.trace_out = L0.trace_buf;
@@ -1099,6 +1116,31 @@ extern "C" int cubics_features(cubics_prob *p, const uint32_t *dom_bits, int32_t
         HIPCHK(hipMemcpyAsync(ddom, p->dev.dom0, n * p->W * 4, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHK(launch_features((const InstDev *)ctx->inst.p, ddom, depth, dout, (int)n, ctx->stream));
     HIPCHK(hipMemcpyAsync(out, dout, n * POLICY_F * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return CUBICS_OK;
+}
+
+extern "C" int cubics_value_features(cubics_prob *p, const uint32_t *dom_bits, int32_t depth, int32_t x,
+                                     float *out) {
+    if (!p || !out) return fail(CUBICS_EINVAL, "NULL argument");
+    if (depth < 0) return fail(CUBICS_EINVAL, "negative depth");
+    if (x < 0 || x >= p->n) return fail(CUBICS_EINVAL, "variable %d out of range", x);
+    if (p->W > 2) return fail(CUBICS_EUNSUPPORTED, "value features need domains of at most 64 values");
+    cubics_ctx *ctx = p->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    const size_t n = (size_t)p->n, nw = n * p->W, nv = 32 * (size_t)p->W;
+    int rc;
+    if ((rc = ctx->inst.ensure(sizeof(InstDev)))) return rc;
+    if ((rc = ctx->rootout.ensure(nw * 4 + nv * POLICY_F * 4 + 64))) return rc;
+    uint32_t *ddom = (uint32_t *)ctx->rootout.p;
+    float *dout = (float *)((char *)ctx->rootout.p + nw * 4);
+    HIPCHK(hipMemcpyAsync(ctx->inst.p, &p->dev, sizeof(InstDev), hipMemcpyHostToDevice, ctx->stream));
+    if (dom_bits)
+        HIPCHK(hipMemcpyAsync(ddom, dom_bits, nw * 4, hipMemcpyHostToDevice, ctx->stream));
+    else
+        HIPCHK(hipMemcpyAsync(ddom, p->dev.dom0, nw * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHK(launch_value_features((const InstDev *)ctx->inst.p, ddom, depth, x, dout, ctx->stream));
+    HIPCHK(hipMemcpyAsync(out, dout, nv * POLICY_F * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return CUBICS_OK;
 }

@@ -163,6 +163,8 @@ struct SearchParams {
     int32_t lds_words;     // per worker
     int32_t nmax, wmax, gmax;
     PolicyDev policy;
+    PolicyDev vpolicy;     // value network (learned value order; lds copy staged per workgroup)
+    int32_t value_order;   // 1 = children of a d-way branching in descending value-network score
     float *trace_out;      // optional trace records [trace_cap][8] (learned policy training)
     unsigned long long *trace_count;
     unsigned long long trace_cap;
@@ -172,5 +174,11 @@ struct SearchParams {
 
 // Trace record (8 floats): features f0..f4, depth, 0, label = log2(1 + nodes below).
 constexpr int TRACE_WORDS = 8;
+
+// Learned value order: per-worker LDS scratch (features of up to 64 values,
+// then their scores) and the scores kept in each trail frame.
+constexpr int VALUE_MAX = 64;
+constexpr int VALUE_LDS_WORDS = VALUE_MAX * POLICY_F + VALUE_MAX;
+constexpr int FRAME_SCORES = VALUE_MAX;
 
 }  // namespace cubics

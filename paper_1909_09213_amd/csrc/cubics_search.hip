@@ -417,6 +417,7 @@ struct Lds {
                      // (staged per task: the fixpoint loop reads two per dirty variable)
     uint32_t *scr;   // 32 words scratch
     float *feat;     // [nmax][4] learned search: the task's static features
+    float *vscr;     // [VALUE_LDS_WORDS] learned value order: value features, then scores
 };
 
 // Process one chunk of binary units in LANE layout.  Returns wave-uniform fail.
@@ -1308,6 +1309,109 @@ DEV int choose_learned(const PolicyDev &pol, const InstDev &I, const Lds &L, int
     return best == ~0ull ? fallback : (int)(best & 0xFFFFFFFFull);
 }
 
+// ------------------------------------------------------- value ordering
+
+// Features of value a of variable x (a live value; lane-parallel over a) at a
+// node whose domains are dom ([n][W] words) and whose unit ranges are
+// [beg, end) for x, at depth `depth`:
+//   g0 = a / d_x (the value's place in the domain),
+//   g1 = mean over x's table constraints of the fraction of the other
+//        variable's current values that x = a supports (1 without tables),
+//   g2 = the smallest of those fractions (1 without tables),
+//   g3 = depth / n,
+//   g4 = |D_x| / d_x.
+// The rows read are those of x's value a in each table (bits over the other
+// variable).
+template <int WM, bool GM>
+DEV void value_features(const InstDev &I, const uint32_t *dom, int beg, int end, int x, int a, int depth,
+                        float (&g)[POLICY_F]) {
+    const int W = I.W;
+    const float inv_d = I.feat_static[4 * x + 2];
+    int px = 0;
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if (k < W) px += __popc(dom[x * W + k]);
+    float sum = 0.f, mn = 1.f;
+    int cnt = 0;
+    for (int i = beg; i < end; ++i) {
+        const Unit u = ld_unit<GM>(I.units, (uint32_t)i);
+        if ((u.tt >> 24) != U_TABLE) continue;
+        const int t = u.tt & 0xFFFFFF;
+        int pt = 0, hit = 0;
+#pragma unroll
+        for (int k = 0; k < WM; ++k) {
+            if (k < W) {
+                const uint32_t dt = dom[t * W + k];
+                pt += __popc(dt);
+                hit += __popc(dt & ldg<GM>(I.rows, (uint32_t)u.p1 + (uint32_t)a * (uint32_t)W + (uint32_t)k));
+            }
+        }
+        if (pt == 0) continue;
+        const float fr = (float)hit / (float)pt;
+        sum += fr;
+        mn = fr < mn ? fr : mn;
+        ++cnt;
+    }
+    g[0] = (float)a * inv_d;
+    g[1] = cnt ? sum / (float)cnt : 1.f;
+    g[2] = cnt ? mn : 1.f;
+    g[3] = (float)depth / (float)(I.n > 0 ? I.n : 1);
+    g[4] = (float)px * inv_d;
+}
+
+// Order-preserving key of a float (larger float -> larger key).
+DEV uint32_t float_key(float y) {
+    const uint32_t u = __float_as_uint(y);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// Scores of the live values of x at the node in L.dom (domains of at most
+// 64 values: lane a <-> value a): the value network on the value features,
+// 16 values per MFMA tile.  Returns this lane's score (lanes of values not
+// in D_x: the lowest key).
+template <int WM, bool GM>
+DEV uint32_t value_scores(const PolicyDev &VP, const InstDev &I, const Lds &L, int x, int depth, int lane) {
+    const int W = I.W;
+    float *ft = L.vscr;                          // [64][5]
+    float *sc = L.vscr + VALUE_MAX * POLICY_F;   // [64]
+    const int beg = uni(L.trig[x]), end = uni(L.trig[x + 1]);
+    const int a = lane;
+    const bool live = a < 32 * W && ((L.dom[x * W + (a >> 5)] >> (a & 31)) & 1u);
+    float g[POLICY_F] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live) value_features<WM, GM>(I, L.dom, beg, end, x, a, depth, g);
+#pragma unroll
+    for (int k = 0; k < POLICY_F; ++k) ft[a * POLICY_F + k] = g[k];
+    wsync();
+    const int row = lane & 15, kq = lane >> 4;
+    for (int base = 0; base < 32 * W; base += 16) {
+        bf16x4 xT;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * kq + j;
+            xT[j] = (short)f2bf(k < POLICY_F ? ft[(base + row) * POLICY_F + k] : 0.f);
+        }
+        const f32x4 acc = mlp_tile<true>(VP, xT, lane, nullptr);
+        if (row == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sc[base + 4 * kq + r] = acc[r] + *VP.b2;
+        }
+    }
+    wsync();
+    return live ? float_key(sc[a]) : 0u;
+}
+
+// The next child of a d-way branching under the learned value order: the
+// remaining value (bit set in v) with the highest score, lowest value on
+// ties.  key: this lane's score key (lane = value).
+template <int WM>
+DEV int pick_value(const uint32_t (&v)[WM], uint32_t key, int lane) {
+    bool avail = false;
+#pragma unroll
+    for (int k = 0; k < WM; ++k) avail |= (k == (lane >> 5)) && ((v[k] >> (lane & 31)) & 1u);
+    const u64 m = avail ? (((u64)(~key) << 32) | (u64)lane) : ~0ull;
+    return (int)(wave_min64(m) & 0xFFFFFFFFull);
+}
+
 // Exploration for trace collection: a uniform pick among the (up to) 4
 // candidates with the smallest domains (ties by index).
 template <int WM>
@@ -1344,7 +1448,7 @@ DEV int choose_explore(const InstDev &I, const Lds &L, int lane, u64 rnd) {
 template <int WM, int FEAT, bool GLOB, bool SEGC, bool GM>
 DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, int kind,
                   Frame<WM> F0, const Lds &L, uint32_t *trail, Counters &C, int lane,
-                  long long t_start, const PolicyDev &LP) {
+                  long long t_start, const PolicyDev &LP, const PolicyDev &VP) {
     const int n = I.n, W = I.W, nw = n * W;
     const int layout = P.layout;
     const uint32_t FW = P.frame_words;
@@ -1364,6 +1468,12 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
     int open_x = 0;
     const bool tracing = FEAT == 2 && P.trace_out != nullptr;
     const bool learned = FEAT == 1 && P.branching == 1;
+    // learned value order (d-way): the value network's score keys of the top
+    // frame's values (lane = value); each frame keeps its own in its last
+    // FRAME_SCORES words
+    const bool vorder = FEAT == 1 && P.value_order != 0;
+    const uint32_t FS = P.frame_words - FRAME_SCORES;
+    uint32_t vkey = 0u;
     if (tracing || learned) {
         for (int i = lane; i < n; i += 64) L.fails[i] = 0u;
         if (learned)
@@ -1401,6 +1511,11 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
             snap_valid = true;
         }
         frame_store_meta<WM>(trail, F, lane);
+        if (vorder) {
+            // the donated frame's node is in L.dom: score its values again
+            vkey = value_scores<WM, GM>(VP, I, L, F.x, F.depth, lane);
+            trail[FS + lane] = vkey;
+        }
         sp = 1;
         need_restore = false;
     }
@@ -1504,6 +1619,10 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
 #pragma unroll
                 for (int k = 0; k < WM; ++k) F.v[k] = dx[k];
                 frame_store_meta<WM>(f, F, lane);
+                if (vorder) {
+                    vkey = value_scores<WM, GM>(VP, I, L, x, depth, lane);
+                    f[FS + lane] = vkey;
+                }
                 if (tracing) {
                     const int px = var_pop<WM>(I, L, x);
                     if (lane < POLICY_F) ((float *)f)[16 + lane] = var_feature(I, I.feat_static, x, lane, depth, px, L.fails[x]);
@@ -1545,7 +1664,10 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                     }
                 }
                 --sp;
-                if (sp > 0) frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
+                if (sp > 0) {
+                    frame_load_meta<WM>(trail + (size_t)(sp - 1) * FW, F);
+                    if (vorder) vkey = trail[(size_t)(sp - 1) * FW + FS + lane];
+                }
                 need_restore = true;
                 snap_valid = false;
                 continue;
@@ -1564,9 +1686,13 @@ DEV void run_task(const SearchParams &P, const InstDev &I, InstCtl *ctl, int b, 
                 }
             } else {
                 int vi = -1;
+                if (vorder) {
+                    vi = pick_value<WM>(F.v, vkey, lane);
+                } else {
 #pragma unroll
-                for (int k = WM - 1; k >= 0; --k)
-                    if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
+                    for (int k = WM - 1; k >= 0; --k)
+                        if (F.v[k]) vi = 32 * k + __ffs(F.v[k]) - 1;
+                }
 #pragma unroll
                 for (int k = 0; k < WM; ++k) {
                     cv[k] = bit_in_word(vi, k);
@@ -2194,26 +2320,31 @@ __global__ __launch_bounds__(512, WM <= 2 ? 4 : 1) void search_kernel(SearchPara
     }
     // learned search: the network's weights staged once per workgroup in LDS
     // (every branching reads all of them)
-    PolicyDev LP = P.policy;
+    PolicyDev LP = P.policy, VP = P.vpolicy;
     uint32_t pol_words = 0;
     if (FEAT == 1) {
-        uint32_t *pw = lds_raw + tab_words;
-        const uint32_t *w1g = (const uint32_t *)P.policy.w1;
-        const uint32_t *w2g = (const uint32_t *)P.policy.w2;
-        for (int t = threadIdx.x; t < POLICY_LDS_WORDS; t += blockDim.x) {
-            uint32_t v = 0u;
-            if (t < POLICY_LDS_B1) v = w1g[t];
-            else if (t < POLICY_LDS_W2) v = __float_as_uint(P.policy.b1[t - POLICY_LDS_B1]);
-            else if (t < POLICY_LDS_B2) v = w2g[t - POLICY_LDS_W2];
-            else if (t == POLICY_LDS_B2) v = __float_as_uint(*P.policy.b2);
-            pw[t] = v;
-        }
+        // the variable network (learned branching) and the value network
+        // (learned value order), each staged when used
+        const auto stage = [&](const PolicyDev &src, uint32_t *pw, PolicyDev &dst) {
+            const uint32_t *w1g = (const uint32_t *)src.w1;
+            const uint32_t *w2g = (const uint32_t *)src.w2;
+            for (int t = threadIdx.x; t < POLICY_LDS_WORDS; t += blockDim.x) {
+                uint32_t v = 0u;
+                if (t < POLICY_LDS_B1) v = w1g[t];
+                else if (t < POLICY_LDS_W2) v = __float_as_uint(src.b1[t - POLICY_LDS_B1]);
+                else if (t < POLICY_LDS_B2) v = w2g[t - POLICY_LDS_W2];
+                else if (t == POLICY_LDS_B2) v = __float_as_uint(*src.b2);
+                pw[t] = v;
+            }
+            dst.w1 = (const uint16_t *)(pw + POLICY_LDS_W1);
+            dst.b1 = (const float *)(pw + POLICY_LDS_B1);
+            dst.w2 = (const uint16_t *)(pw + POLICY_LDS_W2);
+            dst.b2 = (const float *)(pw + POLICY_LDS_B2);
+        };
+        if (P.branching == 1) stage(P.policy, lds_raw + tab_words, LP);
+        if (P.value_order) stage(P.vpolicy, lds_raw + tab_words + POLICY_LDS_WORDS, VP);
         __syncthreads();
-        LP.w1 = (const uint16_t *)(pw + POLICY_LDS_W1);
-        LP.b1 = (const float *)(pw + POLICY_LDS_B1);
-        LP.w2 = (const uint16_t *)(pw + POLICY_LDS_W2);
-        LP.b2 = (const float *)(pw + POLICY_LDS_B2);
-        pol_words = POLICY_LDS_WORDS;
+        pol_words = 2 * POLICY_LDS_WORDS;
     }
     if (wid >= P.nworkers) return;
     uint32_t *base = lds_raw + tab_words + pol_words + (size_t)wave * P.lds_words;
@@ -2233,9 +2364,14 @@ __global__ __launch_bounds__(512, WM <= 2 ? 4 : 1) void search_kernel(SearchPara
     L.trig = (int32_t *)(base + off);
     off += (P.nmax + 2) & ~1;
     L.feat = nullptr;
+    L.vscr = nullptr;
     if (FEAT == 1) {  // the learned search's copy of the task's static features
         L.feat = (float *)(base + off);
         off += 4 * P.nmax;
+        if (P.value_order) {
+            L.vscr = (float *)(base + off);
+            off += VALUE_LDS_WORDS;
+        }
     }
     L.scr = base + off;  // the rest of the worker's words
     uint32_t *trail = P.trail + (size_t)wid * P.trail_words;
@@ -2352,7 +2488,7 @@ __global__ __launch_bounds__(512, WM <= 2 ? 4 : 1) void search_kernel(SearchPara
             if (VAR)
                 run_task_var<WM>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start);
             else
-                run_task<WM, FEAT, GLOB, SEGC, !TL>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start, LP);
+                run_task<WM, FEAT, GLOB, SEGC, !TL>(P, I, ctl, b, kind, F0, L, trail, C, lane, t_start, LP, VP);
         }
         C.tasks += 1;
         flush<WM>(ctl, C, lane);
@@ -2386,6 +2522,19 @@ __global__ void features_kernel(const InstDev *inst, const uint32_t *dom, int de
         for (int k = 0; k < I.W; ++k) pop += __popc(dom[i * I.W + k]);
         for (int k = 0; k < POLICY_F; ++k) out[i * POLICY_F + k] = var_feature(I, I.feat_static, i, k, depth, pop, 0u);
     }
+}
+
+// Value features (value_features) of every value a < 32 W of variable x at a
+// node with domains dom [n][W] and the given depth: out[a][5], zeros for
+// values not in D_x.  One wavefront; domains of at most 64 values.
+__global__ void value_features_kernel(const InstDev *inst, const uint32_t *dom, int depth, int x, float *out) {
+    const InstDev &I = *inst;
+    const int a = threadIdx.x;
+    float g[POLICY_F] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    if (a < 32 * I.W && ((dom[x * I.W + (a >> 5)] >> (a & 31)) & 1u))
+        value_features<2, false>(I, dom, I.trig_off[x], I.trig_off[x + 1], x, a, depth, g);
+    if (a < 32 * I.W)
+        for (int k = 0; k < POLICY_F; ++k) out[a * POLICY_F + k] = g[k];
 }
 
 // Reset the queue and seed it with ROOT tasks: every instance on one ring,
@@ -2576,6 +2725,11 @@ hipError_t launch_features(const InstDev *inst, const uint32_t *dom, int depth, 
                            hipStream_t st) {
     const int blocks = (n + 255) / 256 > 0 ? (n + 255) / 256 : 1;
     hipLaunchKernelGGL(features_kernel, dim3(blocks), dim3(256), 0, st, inst, dom, depth, out);
+    return hipGetLastError();
+}
+hipError_t launch_value_features(const InstDev *inst, const uint32_t *dom, int depth, int x, float *out,
+                                 hipStream_t st) {
+    hipLaunchKernelGGL(value_features_kernel, dim3(1), dim3(64), 0, st, inst, dom, depth, x, out);
     return hipGetLastError();
 }
 hipError_t search_occupancy(int wmax, int *blocks_per_cu, int wpb, size_t lds, bool tl, int variant) {

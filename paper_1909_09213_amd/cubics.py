@@ -42,7 +42,7 @@ class Limits(ctypes.Structure):
         ("policy", ctypes.c_void_p), ("tables_in_lds", ctypes.c_int32), ("explore_pm", ctypes.c_int32),
         ("trace_buf", ctypes.c_void_p), ("trace_capacity", ctypes.c_uint64), ("seed", ctypes.c_uint32),
         ("use_graph", ctypes.c_int32), ("two_way", ctypes.c_int32),
-        ("active_per_xcd", ctypes.c_int32),
+        ("active_per_xcd", ctypes.c_int32), ("value_policy", ctypes.c_void_p),
     ]
 
 
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_prob_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 4
     lib.cubics_root.argtypes = [vp, i32, vp, ctypes.POINTER(i32)]
     lib.cubics_features.argtypes = [vp, vp, i32, vp]
+    lib.cubics_value_features.argtypes = [vp, vp, i32, i32, vp]
     lib.cubics_solve.argtypes = [vp, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
     lib.cubics_solve_batch_static.argtypes = [vp, i32, i32, ctypes.POINTER(Limits), ctypes.POINTER(_Result)]
@@ -131,7 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.cubics_mlp_grad.argtypes = [vp, vp, i32, vp, i32, i64, vp, vp]
     lib.cubics_mlp_train_step.argtypes = [vp, vp, i32, vp, i32, i64, ctypes.c_float, i32, vp]
     for f in ("cubics_create", "cubics_set_stream", "cubics_load", "cubics_prob_info",
-              "cubics_root", "cubics_features", "cubics_solve", "cubics_solve_batch",
+              "cubics_root", "cubics_features", "cubics_value_features", "cubics_solve", "cubics_solve_batch",
               "cubics_solve_batch_static", "cubics_autotune", "cubics_policy_create",
               "cubics_policy_get", "cubics_policy_set", "cubics_mlp_forward", "cubics_mlp_grad",
               "cubics_mlp_train_step"):
@@ -313,11 +314,26 @@ class Context:
         _check(_lib.cubics_features(prob.handle, ptr, depth, out.ctypes.data))
         return out[:prob.n].copy()
 
+    def value_features(self, prob: Problem, dom=None, depth: int = 0, x: int = 0) -> np.ndarray:
+        """cubics_value_features: [32 W, 5] features of the values of x at a
+        node with domains dom ([n, W] device words; None = the initial
+        domains) and the given depth."""
+        nv = 32 * prob.W
+        out = np.zeros((nv, 5), dtype=np.float32)
+        ptr = None
+        if dom is not None:
+            dom = np.ascontiguousarray(dom, dtype=np.uint32)
+            if dom.shape != (prob.n, prob.W):
+                raise ValueError(f"dom must have shape {(prob.n, prob.W)}")
+            ptr = dom.ctypes.data
+        _check(_lib.cubics_value_features(prob.handle, ptr, depth, x, out.ctypes.data))
+        return out
+
     # --------------------------------------------------------------- solve
     def _limits(self, prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                 split_target, sol_capacity, workers, donate, policy, tables_in_lds=0,
                 trace=None, explore_pm=0, seed=0, use_graph=False, two_way=False,
-                no_buffer=False):
+                no_buffer=False, value_policy=None):
         torch = _torch()
         L = Limits()
         L.max_nodes = max_nodes
@@ -329,6 +345,7 @@ class Context:
         L.workers = workers
         L.donate = 1 if donate else 0
         L.policy = policy.handle if policy is not None else None
+        L.value_policy = value_policy.handle if value_policy is not None else None
         L.tables_in_lds = tables_in_lds
         L.use_graph = 1 if use_graph else 0
         L.two_way = 1 if two_way else 0
@@ -361,10 +378,10 @@ class Context:
               max_solutions: int = 0, time_ms: int = 0, branching: int = BRANCH_FIRST_FAIL,
               layout: int = LAYOUT_AUTO, split_target: int = 0, sol_capacity: int = 0,
               workers: int = 0, donate: bool = True, policy=None, tables_in_lds: int = 0,
-              use_graph: bool = False, two_way: bool = False) -> Result:
+              use_graph: bool = False, two_way: bool = False, value_policy=None) -> Result:
         L, buf = self._limits(prob, mode, max_nodes, max_solutions, time_ms, branching, layout,
                               split_target, sol_capacity, workers, donate, policy, tables_in_lds,
-                              use_graph=use_graph, two_way=two_way)
+                              use_graph=use_graph, two_way=two_way, value_policy=value_policy)
         r = _Result()
         _check(_lib.cubics_solve(prob.handle, mode, ctypes.byref(L), ctypes.byref(r)))
         return self._result(r, buf, prob.n)
@@ -375,7 +392,7 @@ class Context:
                     workers: int = 0, donate: bool = True, policy=None, trace=None,
                     explore_pm: int = 0, seed: int = 0, use_graph: bool = False,
                     two_way: bool = False, sol_out=None, static_scratch: bool = False,
-                    active_per_xcd: int = 0):
+                    active_per_xcd: int = 0, value_policy=None):
         """trace: optional torch float32 cuda tensor [cap, 8] receiving trace records.
         sol_out: optional int32 cuda tensor [B, >= max n]; FIRST mode stores
         instance b's solution in row b (no per-instance buffers, and the
@@ -398,7 +415,7 @@ class Context:
                                   split_target, 0 if sol_out is not None else sol_capacity,
                                   workers, donate, policy, 0,
                                   trace if b == 0 else None, explore_pm, seed, use_graph, two_way,
-                                  no_buffer=sol_out is not None)
+                                  no_buffer=sol_out is not None, value_policy=value_policy)
             if sol_out is not None:
                 L.sol_buf = base + b * row
                 L.sol_capacity = 1

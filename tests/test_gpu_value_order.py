@@ -1,0 +1,137 @@
+"""The learned value order: value features against their definition, a
+closed-form value network that reproduces ascending order exactly (the
+oracle's first solution and node count with one worker), and a random
+value network that changes nothing but the order (counts, node and failure
+counts equal the oracle's; first-mode verdicts equal, answers verified)."""
+import sys
+
+import numpy as np
+import pytest
+
+import cspgen
+import oracle
+from oracle import mlp_ref as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cb():
+    from paper_1909_09213_amd import cubics
+    return cubics
+
+
+@pytest.fixture(scope="module")
+def ctx(cb):
+    c = cb.Context(0)
+    yield c
+    c.close()
+
+
+def _values(row):
+    return [32 * w + b for w in range(len(row)) for b in range(32) if (int(row[w]) >> b) & 1]
+
+
+def test_value_features_match_definition(ctx, cb):
+    """cubics_value_features written out from the instance: a / d_x; mean
+    and minimum over x's tables of |{b in D_t : (a, b) allowed}| / |D_t|;
+    depth / n; |D_x| / d_x."""
+    inst = cspgen.rb_sweep(5, base=321, nlo=14, nhi=18, dlo=5, dhi=40, plo=300, phi=500,
+                           tlo=300, thi=450)
+    sub = inst.fix({0: int(inst.lo[0]) + 1})
+    p = ctx.load(sub)
+    failed, dom = ctx.root(p, device_words=True)
+    assert not failed
+    D = [set(_values(row)) for row in dom]
+    for x in range(1, 6):
+        got = ctx.value_features(p, dom, depth=3, x=x)
+        dx = int(inst.dsize[x])
+        fracs = {a: [] for a in D[x]}
+        for c in range(inst.m):
+            i, j = (int(v) for v in inst.scope(c))
+            if x not in (i, j):
+                continue
+            t = j if i == x else i
+            Wj = (int(inst.dsize[j]) + 31) // 32
+            tab = inst.tab(c)
+            for a in D[x]:
+                allowed = 0
+                for b in D[t]:
+                    ai, bj = (a, b) if i == x else (b, a)
+                    allowed += (int(tab[ai * Wj + bj // 32]) >> (bj % 32)) & 1
+                if D[t]:
+                    fracs[a].append(allowed / len(D[t]))
+        for a in range(got.shape[0]):
+            if a not in D[x]:
+                assert np.all(got[a] == 0), (x, a)
+                continue
+            fr = fracs[a]
+            want = [a / dx, np.mean(fr) if fr else 1.0, min(fr) if fr else 1.0, 3 / inst.n, len(D[x]) / dx]
+            assert np.allclose(got[a], want, rtol=1e-5, atol=1e-6), (x, a, got[a], want)
+
+
+def _ascending_network(sign=-1.0):
+    """One live hidden unit reading g0 = a / d_x, output weight `sign`:
+    sign -1 scores smaller values higher (ascending order), +1 the reverse.
+    g0 is strictly increasing in a and keeps distinct bf16 values for
+    d <= 64, so the order is exactly ascending (or descending)."""
+    th = np.zeros(M.NP, dtype=np.float32)
+    th[M.OFF_W1 + 0] = 1.0
+    th[M.OFF_W2 + 0] = sign
+    return th
+
+
+@pytest.mark.parametrize("inst_fn", [lambda: cspgen.queens(20),
+                                     lambda: cspgen.rb(7, n=18, d=12, dens_pm=400, tight_pm=480),
+                                     lambda: cspgen.rb(8, n=12, d=40, dens_pm=500, tight_pm=720),
+                                     lambda: cspgen.rb(9, n=20, d=10, dens_pm=400, tight_pm=470)],
+                         ids=["queens20", "rb_d12", "rb_d40", "rb_unsat"])
+def test_closed_form_value_order_is_ascending(ctx, cb, inst_fn):
+    inst = inst_fn()
+    vp = cb.Policy(ctx, _ascending_network(-1.0))
+    prob = ctx.load(inst)
+    ref = oracle.solve(inst, oracle.MODE_FIRST, sol_cap=1)
+    r = ctx.solve(prob, cb.MODE_FIRST, workers=1, value_policy=vp)
+    assert r.verdict == ref.verdict
+    if ref.verdict == "SAT":
+        assert list(r.solutions[0]) == list(ref.solutions[0])
+    assert (r.nodes, r.fails) == (ref.nodes, ref.fails)
+    # the reversed order finds a (verified) solution too
+    rv = ctx.solve(prob, cb.MODE_FIRST, workers=1, value_policy=cb.Policy(ctx, _ascending_network(1.0)))
+    assert rv.verdict == ref.verdict
+    if rv.verdict == "SAT":
+        assert oracle.verify(inst, rv.solutions[0])
+
+
+def test_value_order_changes_nothing_but_the_order(ctx, cb):
+    vp = cb.Policy(ctx, M.init_theta(13))
+    insts = [cspgen.rb_sweep(i, base=124, nlo=12, nhi=16, dlo=5, dhi=12, plo=400, phi=550,
+                             tlo=300, thi=450) for i in range(24)]
+    probs = [ctx.load(x) for x in insts]
+    cnt = ctx.solve_batch(probs, cb.MODE_COUNT, max_nodes=5_000_000, value_policy=vp)
+    for inst, r in zip(insts, cnt):
+        ref = oracle.solve(inst, oracle.MODE_COUNT, max_nodes=2_000_000)
+        if ref.verdict != "LIMIT":
+            assert (r.count, r.nodes, r.fails) == (ref.count, ref.nodes, ref.fails), inst.name
+    fa = ctx.solve_batch(probs, cb.MODE_FIRST)
+    fb = ctx.solve_batch(probs, cb.MODE_FIRST, value_policy=vp)
+    for inst, a, b in zip(insts, fa, fb):
+        assert a.verdict == b.verdict, inst.name
+        if b.verdict == "SAT":
+            assert oracle.verify(inst, b.solutions[0]), inst.name
+    # all-solutions sets are unchanged
+    q = cspgen.queens(7)
+    r = ctx.solve(ctx.load(q), cb.MODE_ALL, sol_capacity=64, value_policy=vp)
+    ref = oracle.solve(q, oracle.MODE_ALL, sol_cap=64)
+    assert sorted(map(tuple, r.solutions.tolist())) == sorted(map(tuple, ref.solutions.tolist()))
+    assert (r.nodes, r.fails) == (ref.nodes, ref.fails)
+
+
+def test_value_order_rejects_what_it_does_not_support(ctx, cb):
+    vp = cb.Policy(ctx, M.init_theta(1))
+    p = ctx.load(cspgen.queens(6))
+    with pytest.raises(cb.CubicsError):
+        ctx.solve(p, cb.MODE_COUNT, two_way=True, value_policy=vp)
+    wide = ctx.load(cspgen.rb(0, n=5, d=90, dens_pm=900, tight_pm=800))
+    with pytest.raises(cb.CubicsError):
+        ctx.solve(wide, cb.MODE_COUNT, value_policy=vp)
