@@ -22,7 +22,9 @@ core of the host's CPU share).  Further legs, each reported with its own
 figures and outside the timed region: 8-queens all solutions, the RB n=40
 d=16 count configuration (one top-level slice) and 13-queens, the
 all-different + linear family (count capped at 10^6, 65,536 initial
-subproblems), and the learned-vs-first-fail branching experiment.
+subproblems), the learned-vs-first-fail branching experiment on both
+generators, and the learned value order against ascending values
+(find-first).
 """
 from __future__ import annotations
 
@@ -336,6 +338,14 @@ def main():
                 rep.pop("theta")
                 rep["seconds_total"] = round(time.perf_counter() - t, 2)
                 out["learned_vs_first_fail"][fam] = rep
+            # the learned value order (find-first): nodes to the first
+            # solution against ascending values, one worker per instance
+            say("leg learned_value_order (sweep)")
+            t = time.perf_counter()
+            rep = learn.value_experiment(ctx, n_train=4 * args.learned_train, n_eval=2 * args.learned_eval)
+            rep.pop("theta")
+            rep["seconds_total"] = round(time.perf_counter() - t, 2)
+            out["learned_value_order"] = rep
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

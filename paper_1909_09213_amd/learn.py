@@ -214,6 +214,123 @@ def sibling_records(ctx: cb.Context, insts, nodes, n_small: int = 6, n_other: in
     return torch.from_numpy(rec).to(ctx.torch_device)
 
 
+def value_records(ctx: cb.Context, insts, nodes, max_nodes: int = 2_000_000, chunk: int = 4096):
+    """Training records of the value network, from the plain solver: at each
+    sampled node, the first-fail variable x and, for every value a of x, the
+    number of solutions below the child x = a (counted exhaustively, all
+    children in batched launches).  Records [N, 8] (torch, device): the
+    value's 5 features at the node (cubics_value_features), depth, node id,
+    label log2(1 + solutions below x = a).  Nodes with a child over
+    max_nodes, or with domains wider than 64 values, are dropped."""
+    import torch
+    jobs = []  # (node id, value, instance, child init)
+    feats = {}
+    for nid, (k, depth, dom) in enumerate(nodes):
+        inst = insts[k]
+        if dom.shape[1] > 2:
+            continue
+        pops = np.array([sum(bin(int(w)).count("1") for w in row) for row in dom])
+        free = np.flatnonzero(pops >= 2)
+        if free.size == 0:
+            continue
+        x = int(free[np.lexsort((free, pops[free]))[0]])
+        prob = ctx.load(inst.with_init(dom[:, :inst.W]))
+        feats[nid] = (ctx.value_features(prob, dom, depth, x), depth)
+        prob.free()
+        for w in range(dom.shape[1]):
+            for bit in range(32):
+                if (int(dom[x, w]) >> bit) & 1:
+                    init = dom[:, :inst.W].copy()
+                    init[x] = 0
+                    init[x, w] = np.uint32(1 << bit)
+                    jobs.append((nid, 32 * w + bit, inst, init))
+    sols = {}
+    over = set()
+    for c0 in range(0, len(jobs), chunk):
+        part = jobs[c0:c0 + chunk]
+        probs = [ctx.load(inst.with_init(init)) for _, _, inst, init in part]
+        res = ctx.solve_batch(probs, cb.MODE_COUNT, max_nodes=max_nodes)
+        for (nid, a, _, _), r in zip(part, res):
+            if r.verdict == "LIMIT":
+                over.add(nid)
+            sols[(nid, a)] = r.count
+        for p in probs:
+            p.free()
+    rows = []
+    for (nid, a), cnt in sols.items():
+        if nid in over:
+            continue
+        f, depth = feats[nid]
+        rows.append(list(f[a]) + [float(depth), float(nid), float(np.log2(1.0 + cnt))])
+    rec = np.asarray(rows, dtype=np.float32).reshape(-1, 8)
+    return torch.from_numpy(rec).to(ctx.torch_device)
+
+
+def evaluate_first(ctx: cb.Context, insts, vpolicy, max_nodes: int = 2_000_000):
+    """Find-first under the ascending value order and under the value
+    network, each instance searched by one worker (no donation: the same
+    depth-first order every run), all instances in one launch per order.
+    Returns per-order results and launch times; raises if a verdict differs
+    between the two orders where both resolve the instance."""
+    probs = [ctx.load(x) for x in insts]
+    out = {}
+    for name, vp in (("ascending", None), ("learned", vpolicy)):
+        res = ctx.solve_batch(probs, cb.MODE_FIRST, donate=False, max_nodes=max_nodes,
+                              layout=cb.LAYOUT_LANE, value_policy=vp)
+        out[name] = {"results": res, "kernel_ms": res[0].kernel_ms}
+    for i, (a, b) in enumerate(zip(out["ascending"]["results"], out["learned"]["results"])):
+        if a.verdict != "LIMIT" and b.verdict != "LIMIT" and a.verdict != b.verdict:
+            raise AssertionError(f"value order changed the verdict of instance {i}")
+    for p in probs:
+        p.free()
+    return out
+
+
+def value_experiment(ctx: cb.Context, n_train: int = 2000, n_eval: int = 1024, steps: int = 1500,
+                     lr: float = 1e-2, train_base: int = cspgen.SEED_TRAIN + 2000,
+                     eval_base: int = cspgen.SEED_EVAL + 2000, family: str = "sweep"):
+    """Train the value network on solution counts below the children of the
+    first-fail variable at one sampled node of each of n_train instances,
+    then find a first solution of n_eval held-out instances under the
+    ascending order and under the network.  Report: nodes to the first
+    solution on the instances both orders solve (satisfiable ones whose
+    ascending search takes at least n + 1 nodes, i.e. backtracks), their
+    geometric-mean ratio, and the launch times."""
+    make = FAMILIES[family]
+    t0 = time.perf_counter()
+    train_insts = make(train_base, n_train)
+    nodes = sample_nodes(ctx, train_insts, seed=train_base)
+    rec = value_records(ctx, train_insts, nodes)
+    t_label = time.perf_counter() - t0
+    del train_insts
+    t0 = time.perf_counter()
+    vpol, losses = train(ctx, rec, steps=steps, lr=lr)
+    t_train = time.perf_counter() - t0
+    held = make(eval_base, n_eval)
+    ev = evaluate_first(ctx, held, vpol)
+    asc, lrn = ev["ascending"]["results"], ev["learned"]["results"]
+    sat = [i for i in range(n_eval) if asc[i].verdict == "SAT" and lrn[i].verdict == "SAT"]
+    hard = [i for i in sat if asc[i].nodes > held[i].n + 1]
+    r_all = np.array([lrn[i].nodes / asc[i].nodes for i in sat], dtype=np.float64)
+    r_hard = np.array([lrn[i].nodes / asc[i].nodes for i in hard], dtype=np.float64)
+    c7 = centre_labels(rec)[:, 7].double()
+    return {
+        "family": family, "train_instances": n_train, "records": int(rec.shape[0]),
+        "label_variance": float((c7 * c7).mean().item()) if c7.numel() else None,
+        "loss_first": losses[0], "loss_last": losses[-1],
+        "eval_instances": n_eval, "sat_both": len(sat), "backtracking_sat": len(hard),
+        "unsat_both": sum(asc[i].verdict == "UNSAT" and lrn[i].verdict == "UNSAT" for i in range(n_eval)),
+        "nodes_to_first_ascending": int(sum(asc[i].nodes for i in sat)),
+        "nodes_to_first_learned": int(sum(lrn[i].nodes for i in sat)),
+        "node_ratio_geomean_sat": float(np.exp(np.mean(np.log(r_all)))) if len(sat) else None,
+        "node_ratio_geomean_backtracking": float(np.exp(np.mean(np.log(r_hard)))) if len(hard) else None,
+        "fewer_nodes": int((r_hard < 1).sum()), "more_nodes": int((r_hard > 1).sum()),
+        "launch_ms_ascending": ev["ascending"]["kernel_ms"], "launch_ms_learned": ev["learned"]["kernel_ms"],
+        "seconds": {"label": t_label, "train": t_train},
+        "theta": vpol.get().tolist(),
+    }
+
+
 def centre_labels(rec):
     """Copy of the records with column 7 replaced by the label minus the mean
     label of its (instance, depth) group."""
