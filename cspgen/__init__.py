@@ -27,8 +27,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-UNARY, TABLE2, NEQ, LT, QUEENS, ALLDIFF, LINEAR_LE, ALLDIFF_GAC = range(8)
-TYPE_NAMES = ["UNARY", "TABLE2", "NEQ", "LT", "QUEENS", "ALLDIFF", "LINEAR_LE", "ALLDIFF_GAC"]
+UNARY, TABLE2, NEQ, LT, QUEENS, ALLDIFF, LINEAR_LE, ALLDIFF_GAC, LINEAR_LE_AD = range(9)
+TYPE_NAMES = ["UNARY", "TABLE2", "NEQ", "LT", "QUEENS", "ALLDIFF", "LINEAR_LE", "ALLDIFF_GAC",
+              "LINEAR_LE_AD"]
 
 GOLDEN64 = 0x9E3779B97F4A7C15
 
@@ -160,6 +161,15 @@ class Instance:
         out = self.with_init(self.init)
         out.type = np.where(self.type == ALLDIFF, ALLDIFF_GAC, self.type).astype(self.type.dtype)
         out.name = self.name + "_gac"
+        return out
+
+    def with_linear_ad(self) -> "Instance":
+        """Copy whose linear <= constraints are propagated together with the
+        all-different constraints inside their scopes (same constraints,
+        same solutions)."""
+        out = self.with_init(self.init)
+        out.type = np.where(self.type == LINEAR_LE, LINEAR_LE_AD, self.type).astype(self.type.dtype)
+        out.name = self.name + "_lad"
         return out
 
     def full_init(self) -> np.ndarray:

@@ -41,7 +41,8 @@
 #include <string.h>
 
 enum { T_UNARY = 0, T_TABLE2 = 1, T_NEQ = 2, T_LT = 3, T_QUEENS = 4, T_ALLDIFF = 5, T_LINEAR = 6,
-       T_ALLDIFF_GAC = 7 };
+       T_ALLDIFF_GAC = 7, T_LINEAR_AD = 8 };
+enum { AD_GROUPS_MAX = 16 };
 enum { M_FIRST = 0, M_ALL = 1, M_COUNT = 2 };
 enum { V_SAT = 0, V_UNSAT = 1, V_LIMIT = 2 };
 
@@ -323,6 +324,106 @@ static int revise_linear(ctx_t *C, unsigned char *D, int c, unsigned char *chg) 
     return status;
 }
 
+/* sum_t a_t x_t <= b (every a_t > 0) propagated together with the
+   all-different constraints (types 5 and 7) whose scopes lie inside its
+   scope: in constraint order, each one that shares no variable with a group
+   taken before becomes a group (at most AD_GROUPS_MAX).  The variables of a
+   group take pairwise different values, so the group's part of the sum is
+   at least L_g = sum_j a_(j) u_j, with the group's coefficients sorted in
+   descending order and u_1 < u_2 < ... the smallest values of the union of
+   its domains (the largest coefficient meets the smallest value).  The
+   lower bound of the whole sum is
+       S = sum over ungrouped t of a_t min D_t + sum over groups of max(P_g, L_g),
+   P_g the group's sum of a_t min D_t.  Fail if S > b, or if a group's union
+   holds fewer values than the group has variables.  Remove a value v of x_t
+   when a_t v + rest_t > b, with rest_t = S - a_t min D_t for ungrouped t and
+   S - (max(P_g, L_g) - P_g) - a_t min D_t for t in group g: the other
+   variables of the group contribute at least P_g - a_t min D_t.  Every
+   quantity only grows as domains shrink, so the propagator is monotone. */
+static int ad_groups(const ctx_t *C, int c, int *grp /* [k]: group of each scope position or -1 */) {
+    const orc_problem *P = C->P;
+    int k = P->arity[c];
+    const int32_t *sc = P->vars + P->var_off[c];
+    for (int t = 0; t < k; ++t) grp[t] = -1;
+    int G = 0;
+    for (int c2 = 0; c2 < P->m && G < AD_GROUPS_MAX; ++c2) {
+        if (P->type[c2] != T_ALLDIFF && P->type[c2] != T_ALLDIFF_GAC) continue;
+        int k2 = P->arity[c2];
+        const int32_t *s2 = P->vars + P->var_off[c2];
+        int pos[64], ok = k2 <= 64;
+        for (int u = 0; u < k2 && ok; ++u) {
+            pos[u] = -1;
+            for (int t = 0; t < k; ++t)
+                if (sc[t] == s2[u]) pos[u] = t;
+            ok = pos[u] >= 0 && grp[pos[u]] < 0;
+        }
+        if (!ok) continue;
+        for (int u = 0; u < k2; ++u) grp[pos[u]] = G;
+        G++;
+    }
+    return G;
+}
+
+static int cmp_i64_desc(const void *x, const void *y) {
+    int64_t a = *(const int64_t *)x, b = *(const int64_t *)y;
+    return a < b ? 1 : (a > b ? -1 : 0);
+}
+static int cmp_i64_asc(const void *x, const void *y) { return -cmp_i64_desc(x, y); }
+
+static int revise_linear_ad(ctx_t *C, unsigned char *D, int c, unsigned char *chg) {
+    const orc_problem *P = C->P;
+    int k = P->arity[c];
+    const int32_t *sc = P->vars + P->var_off[c];
+    const int64_t *par = P->params + P->par_off[c];
+    int64_t b = par[0];
+    int *grp = (int *)malloc(sizeof(int) * (size_t)k);
+    int64_t *vals = (int64_t *)malloc(sizeof(int64_t) * (size_t)64 * (size_t)C->dmax);
+    int G = ad_groups(C, c, grp);
+    int64_t S = 0, delta[AD_GROUPS_MAX];
+    int status = 0;
+    for (int t = 0; t < k; ++t) {
+        if (dom_min(C, D, sc[t]) < 0) { status = 2; goto done; }
+        if (grp[t] < 0) S += par[1 + t] * value_of(C, sc[t], dom_min(C, D, sc[t]));
+    }
+    for (int g = 0; g < G; ++g) {
+        int64_t Pg = 0, coef[64];
+        int kg = 0, nv = 0;
+        for (int t = 0; t < k; ++t) {
+            if (grp[t] != g) continue;
+            int x = sc[t];
+            Pg += par[1 + t] * value_of(C, x, dom_min(C, D, x));
+            coef[kg++] = par[1 + t];
+            for (int a = 0; a < P->dsize[x]; ++a)
+                if (D[(int64_t)x * C->dmax + a]) vals[nv++] = value_of(C, x, a);
+        }
+        qsort(vals, (size_t)nv, sizeof(int64_t), cmp_i64_asc);
+        int nu = 0;  /* distinct values, in place */
+        for (int q = 0; q < nv; ++q)
+            if (nu == 0 || vals[q] != vals[nu - 1]) vals[nu++] = vals[q];
+        if (nu < kg) { status = 2; goto done; }
+        qsort(coef, (size_t)kg, sizeof(int64_t), cmp_i64_desc);
+        int64_t Lg = 0;
+        for (int j = 0; j < kg; ++j) Lg += coef[j] * vals[j];
+        int64_t mx = Lg > Pg ? Lg : Pg;
+        S += mx;
+        delta[g] = mx - Pg;
+    }
+    if (S > b) { status = 2; goto done; }
+    for (int t = 0; t < k; ++t) {
+        int x = sc[t];
+        int64_t at = par[1 + t];
+        int64_t rest = S - at * value_of(C, x, dom_min(C, D, x)) - (grp[t] >= 0 ? delta[grp[t]] : 0);
+        for (int a = 0; a < P->dsize[x]; ++a) {
+            unsigned char *cell = D + (int64_t)x * C->dmax + a;
+            if (*cell && at * value_of(C, x, a) + rest > b) { *cell = 0; chg[x] = 1; status |= 1; }
+        }
+    }
+done:
+    free(vals);
+    free(grp);
+    return status;
+}
+
 /* ----------------------------------------------------------- propagation */
 
 static void enqueue(ctx_t *C, int p) {
@@ -347,11 +448,12 @@ static int propagate(ctx_t *C, unsigned char *D, unsigned char *chg) {
         C->st.revisions++;
         int c = C->prop[p].con, ty = C->P->type[c];
         int status;
-        if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC) {
+        if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC || ty == T_LINEAR_AD) {
             memset(chg, 0, (size_t)C->n);
-            status = ty == T_ALLDIFF   ? revise_alldiff(C, D, c, chg)
-                     : ty == T_LINEAR ? revise_linear(C, D, c, chg)
-                                      : revise_alldiff_gac(C, D, c, chg);
+            status = ty == T_ALLDIFF     ? revise_alldiff(C, D, c, chg)
+                     : ty == T_LINEAR    ? revise_linear(C, D, c, chg)
+                     : ty == T_LINEAR_AD ? revise_linear_ad(C, D, c, chg)
+                                         : revise_alldiff_gac(C, D, c, chg);
             if (status & 2) goto fail;
             for (int v = 0; v < C->n; ++v)
                 if (chg[v]) enqueue_var(C, v);
@@ -464,13 +566,13 @@ static int setup(ctx_t *C, const orc_problem *P) {
             if (k != 2 || sc[0] == sc[1]) return -1;
             C->prop[C->nprop].con = c; C->prop[C->nprop].dir = 0; C->nprop++;
             C->prop[C->nprop].con = c; C->prop[C->nprop].dir = 1; C->nprop++;
-        } else if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC) {
+        } else if (ty == T_ALLDIFF || ty == T_LINEAR || ty == T_ALLDIFF_GAC || ty == T_LINEAR_AD) {
             if (k < 1) return -1;
-            if (ty == T_ALLDIFF_GAC)  /* a scope is a set of variables */
+            if (ty == T_ALLDIFF_GAC || ty == T_LINEAR_AD)  /* a scope is a set of variables */
                 for (int t = 0; t < k; ++t)
                     for (int u = t + 1; u < k; ++u)
                         if (sc[t] == sc[u]) return -1;
-            if (ty == T_LINEAR)
+            if (ty == T_LINEAR || ty == T_LINEAR_AD)
                 for (int t = 0; t < k; ++t)
                     if (P->params[P->par_off[c] + 1 + t] <= 0) return -1;
             C->prop[C->nprop].con = c; C->prop[C->nprop].dir = 0; C->nprop++;
@@ -637,7 +739,8 @@ int orc_verify(const orc_problem *P, const int32_t *x) {
                 for (int w = u + 1; w < k; ++w)
                     if (x[sc[u]] == x[sc[w]]) return 0;
             break;
-        case T_LINEAR: {
+        case T_LINEAR:
+        case T_LINEAR_AD: {
             int64_t s = 0;
             for (int u = 0; u < k; ++u) s += par[1 + u] * (int64_t)x[sc[u]];
             if (s > par[0]) return 0;

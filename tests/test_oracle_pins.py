@@ -474,9 +474,59 @@ def _def_fixpoint(inst, D):
                     if keep != D[u]:
                         D[u] = keep
                         changed = True
+            elif ty == 8:
+                r = _linear_ad_rule(inst, c, D)
+                if r is None:
+                    return None
+                changed |= r
             if any(not D[u] for u in range(n)):
                 return None
     return D
+
+
+def _linear_ad_rule(inst, c, D):
+    """sum a_t x_t <= b together with the all-different constraints inside
+    its scope (constraint order, disjoint ones only).  A group's part of the
+    sum is bounded below by its smallest value over every assignment of
+    pairwise different values from the union of its domains (enumerated
+    here), and by the sum of its minima; a value v of x_t goes when a_t v plus
+    the bound of everything else exceeds b, the rest of t's group counted by
+    its minima.  Returns None on failure, else whether a domain shrank."""
+    sc = [int(v) for v in inst.scope(c)]
+    par = [int(v) for v in inst.par(c)]
+    b, coef = par[0], par[1:]
+    grp = [-1] * len(sc)
+    G = 0
+    for c2 in range(inst.m):
+        if int(inst.type[c2]) not in (5, 7) or G == 16:
+            continue
+        s2 = [int(v) for v in inst.scope(c2)]
+        if all(u in sc and grp[sc.index(u)] < 0 for u in s2):
+            for u in s2:
+                grp[sc.index(u)] = G
+            G += 1
+    S = sum(a * min(D[u]) for a, u, g in zip(coef, sc, grp) if g < 0)
+    delta = []
+    for g in range(G):
+        pos = [t for t in range(len(sc)) if grp[t] == g]
+        union = sorted(set().union(*[D[sc[t]] for t in pos]))
+        if len(union) < len(pos):
+            return None
+        Pg = sum(coef[t] * min(D[sc[t]]) for t in pos)
+        Lg = min(sum(coef[t] * v for t, v in zip(pos, vals))
+                 for vals in itertools.permutations(union, len(pos)))
+        S += max(Pg, Lg)
+        delta.append(max(Pg, Lg) - Pg)
+    if S > b:
+        return None
+    changed = False
+    for t, (a, u) in enumerate(zip(coef, sc)):
+        rest = S - a * min(D[u]) - (delta[grp[t]] if grp[t] >= 0 else 0)
+        keep = {v for v in D[u] if a * v + rest <= b}
+        if keep != D[u]:
+            D[u] = keep
+            changed = True
+    return changed
 
 
 def _def_search(inst, two_way=False):
@@ -684,3 +734,80 @@ def test_two_way_branching_counts_and_nodes():
         b = oracle.solve(inst, oracle.MODE_COUNT, two_way=True)
         s = _def_search(inst, two_way=True)
         assert (b.count, b.nodes, b.fails) == (s["count"], s["nodes"], s["fails"]), n
+
+
+# ------------------------------------------- linear <= with all-different
+
+@pytest.mark.parametrize("n,d", [(3, 5), (4, 6), (5, 5), (6, 9)])
+def test_linear_ad_root_fails_below_the_distinct_minimum(n, d):
+    """n variables over 0..d-1, all different, sum x_i <= b: pairwise
+    different values sum to at least 0 + 1 + ... + (n-1) = n(n-1)/2.  With
+    b one below it the all-different-aware propagator fails at the root (1
+    node, 1 failure) while the plain bound (0) has to search; with b equal
+    to it the solutions are the n! orderings of 0..n-1."""
+    lo_sum = n * (n - 1) // 2
+    for b in (lo_sum - 1, lo_sum):
+        cons = [(5, tuple(range(n)), (), ()), (6, tuple(range(n)), (b,) + (1,) * n, ())]
+        plain = _custom(n, [0] * n, [d] * n, cons)
+        ad = _custom(n, [0] * n, [d] * n, [cons[0], (8, tuple(range(n)), (b,) + (1,) * n, ())])
+        rp = oracle.solve(plain, oracle.MODE_COUNT)
+        ra = oracle.solve(ad, oracle.MODE_COUNT)
+        assert ra.count == rp.count
+        if b < lo_sum:
+            assert ra.count == 0 and (ra.nodes, ra.fails) == (1, 1)
+            assert rp.nodes > 1
+        else:
+            assert ra.count == math.factorial(n)
+            assert ra.nodes <= rp.nodes
+
+
+def test_linear_ad_weighted_minimum():
+    """Coefficients (3, 2, 1) over 0..4, all different: the smallest weighted
+    sum of three different values puts the largest coefficient on the
+    smallest value, 3*0 + 2*1 + 1*2 = 4 (rearrangement).  b = 3 fails at the
+    root; b = 4 has exactly the solution (0, 1, 2)."""
+    for b, want in ((3, 0), (4, 1)):
+        inst = _custom(3, [0] * 3, [5] * 3, [(5, (0, 1, 2), (), ()), (8, (0, 1, 2), (b, 3, 2, 1), ())])
+        r = oracle.solve(inst, oracle.MODE_ALL, sol_cap=10)
+        assert r.count == want
+        if want == 0:
+            assert (r.nodes, r.fails) == (1, 1)
+        else:
+            assert r.solutions.tolist() == [[0, 1, 2]]
+
+
+@pytest.mark.parametrize("idx", range(6))
+def test_linear_ad_counts_match_brute_force(idx):
+    """The global family's twins with the all-different-aware linear
+    propagator: the same solution counts as brute force and as the plain
+    linear propagator, every solution verified, and root domains inside the
+    plain propagator's.  (Node counts may go either way: first-fail picks
+    its variables from different domain sizes.)"""
+    g = cspgen.global_twin(idx)
+    ad = g.with_linear_ad()
+    bf = oracle.brute(g, limit=10 ** 8)
+    assert bf is not None
+    rp = oracle.solve(g, oracle.MODE_COUNT)
+    ra = oracle.solve(ad, oracle.MODE_COUNT)
+    assert ra.count == rp.count == bf[0]
+    ref = oracle.solve(ad, oracle.MODE_ALL, sol_cap=bf[0] + 1)
+    assert ref.n_written == bf[0]
+    for row in ref.solutions:
+        assert oracle.verify(g, row)
+    fp, bp, _ = oracle.root(g)
+    fa, ba, _ = oracle.root(ad)
+    assert fa or not fp
+    if not fa:
+        assert np.all((ba & ~bp) == 0)
+
+
+@pytest.mark.parametrize("idx", range(12))
+def test_linear_ad_node_counts_match_independent_search(idx):
+    """Small twins (5 variables over 0..4, all-different over 3) searched by
+    the independent definition-level search, whose group bound enumerates
+    every assignment of pairwise different values: equal counts, nodes and
+    failures."""
+    ad = cspgen.global_twin(idx, n=5, d=5, k_ad=3).with_linear_ad()
+    s = _def_search(ad)
+    r = oracle.solve(ad, oracle.MODE_COUNT)
+    assert (r.count, r.nodes, r.fails) == (s["count"], s["nodes"], s["fails"]), idx
