@@ -60,6 +60,16 @@ extern "C" {
  *              at most 64 variables, else CUBICS_EUNSUPPORTED
  *   LINEAR_LE  scope (v_0..v_{k-1}); params {b, a_0..a_{k-1}}, every a_t > 0:
  *                           sum_t a_t x_{v_t} <= b
+ *   LINEAR_LE_AD  the same constraint over distinct variables (a repeated
+ *              variable is CUBICS_EINVAL), propagated together with the
+ *              ALLDIFF / ALLDIFF_GAC constraints whose variables all lie in
+ *              its scope (in constraint order, each sharing no variable with
+ *              one taken before; at most 16 of at most 64 variables).  Such
+ *              a group's part of the sum is at least its coefficients in
+ *              descending order times the smallest values of the union of
+ *              its domains in ascending order: the stronger reasoning over
+ *              global constraints that Sec. 3 names as a direction.  Same
+ *              solutions as LINEAR_LE; fewer or equal surviving values.
  */
 enum {
     CUBICS_UNARY = 0,
@@ -69,7 +79,8 @@ enum {
     CUBICS_QUEENS = 4,
     CUBICS_ALLDIFF = 5,
     CUBICS_LINEAR_LE = 6,
-    CUBICS_ALLDIFF_GAC = 7
+    CUBICS_ALLDIFF_GAC = 7,
+    CUBICS_LINEAR_LE_AD = 8
 };
 
 /* solve modes */
@@ -92,7 +103,7 @@ enum { CUBICS_LAYOUT_AUTO = 0, CUBICS_LAYOUT_LANE = 1, CUBICS_LAYOUT_SEG = 2, CU
 
 /* Supported range: 1 <= d_i <= 256 values per variable (at most 8 32-bit
    words per domain); n <= 1024 variables with n * ceil(dmax/32) <= 4096;
-   at most 65535 global (ALLDIFF / ALLDIFF_GAC / LINEAR_LE) constraints per
+   at most 65535 global (ALLDIFF / ALLDIFF_GAC / LINEAR_LE / LINEAR_LE_AD) constraints per
    instance; ALLDIFF_GAC over at most 64 variables. */
 #define CUBICS_MAX_DOMAIN 256
 #define CUBICS_MAX_VARS 1024

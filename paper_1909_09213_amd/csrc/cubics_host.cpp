@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -345,9 +346,14 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                     tight_sum[i] += 3.0 / dj; tight_sum[j] += 3.0 / di;
                 }
             }
-        } else if (ty == CUBICS_ALLDIFF || ty == CUBICS_ALLDIFF_GAC || ty == CUBICS_LINEAR_LE) {
+        } else if (ty == CUBICS_ALLDIFF || ty == CUBICS_ALLDIFF_GAC || ty == CUBICS_LINEAR_LE ||
+                   ty == CUBICS_LINEAR_LE_AD) {
+            const bool lin = ty == CUBICS_LINEAR_LE || ty == CUBICS_LINEAR_LE_AD;
             GDesc g;
-            g.type = ty == CUBICS_ALLDIFF ? G_ALLDIFF : ty == CUBICS_ALLDIFF_GAC ? G_ALLDIFF_GAC : G_LINEAR;
+            g.type = ty == CUBICS_ALLDIFF       ? G_ALLDIFF
+                     : ty == CUBICS_ALLDIFF_GAC ? G_ALLDIFF_GAC
+                     : ty == CUBICS_LINEAR_LE   ? G_LINEAR
+                                                : G_LINEAR_AD;
             if (ty == CUBICS_ALLDIFF_GAC) {
                 if (k > GAC_MAX_K)
                     return fail(CUBICS_EUNSUPPORTED, "constraint %d: ALLDIFF_GAC over %d > %d variables", c, k,
@@ -357,8 +363,8 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
             g.k = k;
             g.scope_off = (int32_t)gscope.size();
             g.coef_off = (int32_t)gcoef.size();
-            if (ty == CUBICS_LINEAR_LE) last_lin_b = g.coef_off;
-            if (ty != CUBICS_LINEAR_LE) {
+            if (lin) last_lin_b = g.coef_off;
+            if (!lin) {
                 // the scope's domains are compared in value space: base = the
                 // smallest lo; the span must fit the instance's domain words
                 int base = lo[sc[0]], top = lo[sc[0]] + dsize[sc[0]];
@@ -373,11 +379,15 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
                 for (int t = 0; t < k; ++t) tight_sum[sc[t]] += (double)(k - 1) / dsize[sc[t]];
             } else {
                 if (npar != 1 + k || !par) return fail(CUBICS_EINVAL, "constraint %d: LINEAR_LE needs 1+k parameters", c);
-                double mag = std::fabs((double)par[0]);
+                double mag = std::fabs((double)par[0]), vall = 0;
+                for (int t = 0; t < k; ++t)
+                    vall = std::max(vall, std::max(std::fabs((double)lo[sc[t]]),
+                                                   std::fabs((double)lo[sc[t]] + dsize[sc[t]] - 1)));
                 for (int t = 0; t < k; ++t) {
                     if (par[1 + t] <= 0) return fail(CUBICS_EINVAL, "constraint %d: non-positive coefficient", c);
                     const double vmax = std::max(std::fabs((double)lo[sc[t]]), std::fabs((double)lo[sc[t]] + dsize[sc[t]] - 1));
-                    mag += (double)par[1 + t] * vmax;
+                    // a group bound pairs a coefficient with any value of its group
+                    mag += (double)par[1 + t] * (ty == CUBICS_LINEAR_LE_AD ? vall : vmax);
                 }
                 if (mag > 4.0e18) return fail(CUBICS_EUNSUPPORTED, "constraint %d: linear sum may overflow int64", c);
                 double maxsum = 0;
@@ -389,6 +399,50 @@ extern "C" int cubics_load(cubics_ctx *ctx, int32_t n, const int32_t *lo, const 
             for (int t = 0; t < k; ++t) {
                 gscope.push_back(sc[t]);
                 deg[sc[t]]++;
+            }
+            if (ty == CUBICS_LINEAR_LE_AD) {
+                // groups: the all-different constraints (ALLDIFF, ALLDIFF_GAC)
+                // whose variables all lie in the scope, in constraint order,
+                // each sharing no variable with a group taken before; at most
+                // AD_GROUPS_MAX, each of at most 64 listed variables
+                std::vector<int> pos_of(n, -1), grp(k, -1);
+                for (int t = 0; t < k; ++t) {
+                    if (pos_of[sc[t]] >= 0)
+                        return fail(CUBICS_EINVAL, "constraint %d: LINEAR_LE_AD scope repeats variable %d", c, sc[t]);
+                    pos_of[sc[t]] = t;
+                }
+                std::vector<std::vector<int>> groups;
+                for (int c2 = 0; c2 < m && (int)groups.size() < AD_GROUPS_MAX; ++c2) {
+                    if (type[c2] != CUBICS_ALLDIFF && type[c2] != CUBICS_ALLDIFF_GAC) continue;
+                    const int k2 = arity[c2];
+                    if (k2 < 1 || k2 > 64 || var_off[c2 + 1] - var_off[c2] != k2) continue;
+                    const int32_t *s2 = vars + var_off[c2];
+                    std::vector<int> pos;
+                    bool ok = true;
+                    for (int u = 0; u < k2 && ok; ++u) {
+                        const int t = (s2[u] >= 0 && s2[u] < n) ? pos_of[s2[u]] : -1;
+                        ok = t >= 0 && grp[t] < 0;
+                        if (ok && std::find(pos.begin(), pos.end(), t) == pos.end()) pos.push_back(t);
+                    }
+                    if (!ok) continue;
+                    for (int t : pos) grp[t] = (int)groups.size();
+                    groups.push_back(pos);
+                }
+                for (int t = 0; t < k; ++t) gscope.push_back(grp[t]);
+                gcoef.push_back((int64_t)groups.size());
+                for (const std::vector<int> &pos : groups) {
+                    int base = lo[sc[pos[0]]];
+                    std::vector<int64_t> a;
+                    for (int t : pos) {
+                        base = std::min(base, (int)lo[sc[t]]);
+                        a.push_back(par[1 + t]);
+                        gscope.push_back(t);
+                    }
+                    std::sort(a.begin(), a.end(), std::greater<int64_t>());
+                    gcoef.push_back(base);
+                    gcoef.push_back((int64_t)pos.size());
+                    gcoef.insert(gcoef.end(), a.begin(), a.end());
+                }
             }
             gdesc.push_back(g);
             if (gdesc.size() > 65535) return fail(CUBICS_EUNSUPPORTED, "more than 65535 global constraints");

@@ -14,7 +14,10 @@ enum UnitType : int32_t {
     U_LT_LB = 4,   // keep a >= min(D_src) - p0 + 1
     U_QUEENS = 5,  // p0 = k, p1 = delta: a conflicts with b iff a - b - delta in {0, k, -k}
 };
-enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2, G_ALLDIFF_GAC = 3 };
+enum GlobalType : int32_t { G_ALLDIFF = 1, G_LINEAR = 2, G_ALLDIFF_GAC = 3, G_LINEAR_AD = 4 };
+// A linear <= constraint bounded with the all-different groups inside its
+// scope holds at most this many groups, each of at most 64 variables.
+constexpr int AD_GROUPS_MAX = 16;
 constexpr int GAC_MAX_K = 64;     // variables of one GAC all-different (one lane each)
 constexpr int SCRATCH_WORDS = 32;      // per-worker LDS scratch
 constexpr int SCRATCH_GAC_WORDS = 96;  // ... when a GAC all-different is present
@@ -37,8 +40,12 @@ struct Unit {
 struct GDesc {
     int32_t type;
     int32_t k;         // arity
-    int32_t scope_off; // into gscope
-    int32_t coef_off;  // into gcoef: b, a_0..a_{k-1} (LINEAR)
+    int32_t scope_off; // into gscope: v_0..v_{k-1}; LINEAR_AD also group[k]
+                       // (-1 = ungrouped), then each group's scope positions
+    int32_t coef_off;  // into gcoef: b, a_0..a_{k-1} (LINEAR); LINEAR_AD also
+                       // G, then per group: base value, k_g, the group's
+                       // coefficients in descending order.  ALLDIFF*: the
+                       // scope's smallest lo (no gcoef entries)
 };
 
 // Per-instance read-only descriptor (device memory).  All pointers are device

@@ -888,6 +888,170 @@ DEV bool revise_linear(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt,
     return false;
 }
 
+// Position (0-based) of the r-th set bit of x, r < popcount(x): halve the
+// window by the population of its low half.
+DEV int select32(uint32_t x, int r) {
+    int pos = 0;
+#pragma unroll
+    for (int s = 16; s >= 1; s >>= 1) {
+        const int c = __popc(x & ((1u << s) - 1u));
+        if (r >= c) {
+            r -= c;
+            x >>= s;
+            pos += s;
+        }
+    }
+    return pos;
+}
+
+// Keep the values v of x_v (domain d, minimum index mn) with
+// a * (lo_v + v) <= slack; the bound never falls below the minimum since the
+// caller checked S <= b.
+template <int WM>
+DEV void linear_cut(const InstDev &I, const Lds &L, u64 *nxt, Counters &C, int v, uint32_t (&d)[WM],
+                    long long at, long long slack) {
+    const int W = I.W;
+    const long long mx = (long long)I.lo[v] + high_w(d, W);
+    const long long ubi = at * mx > slack ? floor_div(slack, at) - I.lo[v] : 32LL * W;
+    if (ubi < 32LL * W - 1) {
+        const int ub = (int)ubi;
+        bool ch = false;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            if (w < W) {
+                uint32_t nd = d[w] & mask_le(ub, w);
+                ch |= nd != d[w];
+                d[w] = nd;
+            }
+        }
+        if (ch) {
+#pragma unroll
+            for (int w = 0; w < WM; ++w)
+                if (w < W) L.dom[v * W + w] = d[w];
+            atomicOr(&nxt[v >> 6], 1ull << (v & 63));
+            C.bytes += 4ull * W;
+        }
+    }
+}
+
+// sum a_t x_t <= b bounded with the all-different groups inside the scope.
+// A group's variables take pairwise different values, so its part of the sum
+// is at least L_g = sum_j c_j u_j: c_1 >= c_2 >= ... its coefficients, u_1 <
+// u_2 < ... the smallest values of the union of its domains (rearrangement:
+// the largest coefficient meets the smallest value).  With P_g the group's
+// sum of a_t min D_t,
+//   S = sum over ungrouped t of a_t min D_t + sum_g max(P_g, L_g);
+// fail if S > b or a group's union holds fewer values than the group has
+// variables.  x_t keeps the values v with a_t v + rest_t <= b, rest_t =
+// S - a_t min D_t, less max(P_g, L_g) - P_g for t in group g (the rest of the
+// group counted by its minima).  One lane per group variable (k_g <= 64);
+// lane g keeps group g's excess max(P_g, L_g) - P_g.
+template <int WM>
+DEV bool revise_linear_ad(const InstDev &I, const GDesc &g, const Lds &L, u64 *nxt, Counters &C, int lane) {
+    const int W = I.W, k = g.k;
+    const int32_t *sc = I.gscope + g.scope_off, *grp = sc + k;
+    const int64_t *co = I.gcoef + g.coef_off;
+    const long long b = co[0];
+    const int G = (int)co[1 + k];
+    long long part = 0;
+    for (int t = lane; t < k; t += 64) {
+        if (grp[t] >= 0) continue;
+        const int v = sc[t];
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        part += (long long)co[1 + t] * (long long)(I.lo[v] + low_w(d, W));
+    }
+    long long S = wave_sum64(part), excess = 0;
+    C.rev += lane == 0 ? 1 : 0;
+    C.bytes += lane == 0 ? 4ull * (u64)k * W : 0ull;
+    const int32_t *pos = grp + k;
+    int off = 2 + k;
+    for (int q = 0; q < G; ++q) {
+        const int base = (int)co[off], kg = (int)co[off + 1];
+        const int64_t *cg = co + off + 2;
+        uint32_t U[WM];
+        long long pg = 0;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) U[w] = 0u;
+        if (lane < kg) {
+            const int t = pos[lane], v = sc[t];
+            uint32_t d[WM];
+#pragma unroll
+            for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+            pg = (long long)co[1 + t] * (long long)(I.lo[v] + low_w(d, W));
+            const int sft = I.lo[v] - base;
+            if (sft) {
+                shl_w(d, sft, U);
+            } else {
+#pragma unroll
+                for (int w = 0; w < WM; ++w) U[w] = d[w];
+            }
+        }
+        int upop = 0;
+#pragma unroll
+        for (int w = 0; w < WM; ++w) {
+            if (w < W) {
+                U[w] = wave_or(U[w]);
+                upop += __popc(U[w]);
+            }
+        }
+        if (upop < kg) return true;  // wave-uniform
+        long long lg = 0;
+        if (lane < kg) {
+            int r = lane, idx = 0;
+            bool found = false;
+#pragma unroll
+            for (int w = 0; w < WM; ++w) {
+                const int pc = __popc(U[w]);
+                if (!found && r < pc) {
+                    idx = 32 * w + select32(U[w], r);
+                    found = true;
+                } else if (!found) {
+                    r -= pc;
+                }
+            }
+            lg = (long long)cg[lane] * (long long)(base + idx);
+        }
+        const long long P = wave_sum64(pg), Lg = wave_sum64(lg);
+        const long long mx = Lg > P ? Lg : P;
+        S += mx;
+        excess = lane == q ? mx - P : excess;
+        pos += kg;
+        off += 2 + kg;
+    }
+    if (S > b) return true;
+    for (int t = lane; t < k; t += 64) {
+        if (grp[t] >= 0) continue;
+        const int v = sc[t];
+        uint32_t d[WM];
+#pragma unroll
+        for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+        const long long at = co[1 + t];
+        const long long mn = (long long)I.lo[v] + low_w(d, W);
+        linear_cut<WM>(I, L, nxt, C, v, d, at, b - (S - at * mn));
+    }
+    pos = grp + k;
+    off = 2 + k;
+    for (int q = 0; q < G; ++q) {
+        const int kg = (int)co[off + 1];
+        const long long ex = readlane64((u64)excess, q);
+        if (lane < kg) {
+            const int t = pos[lane], v = sc[t];
+            uint32_t d[WM];
+#pragma unroll
+            for (int w = 0; w < WM; ++w) d[w] = w < W ? L.dom[v * W + w] : 0u;
+            const long long at = co[1 + t];
+            const long long mn = (long long)I.lo[v] + low_w(d, W);
+            linear_cut<WM>(I, L, nxt, C, v, d, at, b - (S - ex - at * mn));
+        }
+        pos += kg;
+        off += 2 + kg;
+    }
+    wsync();
+    return false;
+}
+
 // ------------------------------------------------------------ propagate
 
 // Revise to the fixpoint.  L.dA holds the initially dirty variables.
@@ -949,9 +1113,10 @@ DEV bool propagate(const InstDev &I, const Lds &L, int layout, Counters &C, int 
                     const int gi = w * 64 + __ffsll((long long)bits) - 1;
                     bits &= bits - 1;
                     const GDesc g = I.gdesc[gi];
-                    const bool f = g.type == G_ALLDIFF  ? revise_alldiff<WM>(I, g, L, nxt, C, lane)
-                                   : g.type == G_LINEAR ? revise_linear<WM>(I, g, L, nxt, C, lane)
-                                                        : revise_alldiff_gac<WM>(I, g, L, nxt, C, lane);
+                    const bool f = g.type == G_ALLDIFF     ? revise_alldiff<WM>(I, g, L, nxt, C, lane)
+                                   : g.type == G_LINEAR    ? revise_linear<WM>(I, g, L, nxt, C, lane)
+                                   : g.type == G_LINEAR_AD ? revise_linear_ad<WM>(I, g, L, nxt, C, lane)
+                                                           : revise_alldiff_gac<WM>(I, g, L, nxt, C, lane);
                     if (f) return true;
                 }
             }
