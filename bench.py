@@ -190,7 +190,35 @@ def leg_global(ctx, cb, cspgen):
     return {"workload": "200 vars over 0..255, 10 all-different x 20 vars, 30 linear <= "
                         "(seed 4 index 0), count capped at 10^6, 65,536 initial subproblems",
             "count": r.count, "verdict": r.verdict, "nodes": r.nodes, "tasks": r.tasks,
-            "kernel_ms": round(r.kernel_ms, 3), "nodes_per_s": r.nodes / (r.kernel_ms * 1e-3)}
+            "fails": r.fails, "kernel_ms": round(r.kernel_ms, 3),
+            "nodes_per_s": r.nodes / (r.kernel_ms * 1e-3)}
+
+
+def leg_linear_ad(ctx, cb, cspgen):
+    """Linear <= bounded with the all-different groups in its scope against
+    the plain bound: 256 global twins (8 vars over 0..7, 2 all-different x 5,
+    3 linear <=) counted exhaustively in one batch, and the full global
+    instance's count capped at 10^6."""
+    twins = [cspgen.global_twin(i) for i in range(256)]
+    out = {"workload": "256 global twins (n=8, d=8, 2 all-different x 5, 3 linear <=) count-all; "
+                       "global family (seed 4 index 0) count capped at 10^6"}
+    counts = {}
+    for tag, insts in (("plain", twins), ("linear_ad", [x.with_linear_ad() for x in twins])):
+        probs = [ctx.load(x) for x in insts]
+        res = ctx.solve_batch(probs, cb.MODE_COUNT)
+        counts[tag] = [r.count for r in res]
+        out[f"twins_{tag}_nodes"] = sum(r.nodes for r in res)
+        out[f"twins_{tag}_fails"] = sum(r.fails for r in res)
+        out[f"twins_{tag}_kernel_ms"] = round(res[0].kernel_ms, 3)
+        for p in probs:
+            p.free()
+    assert counts["plain"] == counts["linear_ad"]
+    g = ctx.load(cspgen.global_family(0).with_linear_ad())
+    r = ctx.solve(g, cb.MODE_COUNT, max_solutions=10 ** 6, split_target=65536)
+    assert r.count == 10 ** 6, r.count
+    out.update({"global_linear_ad_nodes": r.nodes, "global_linear_ad_fails": r.fails,
+                "global_linear_ad_kernel_ms": round(r.kernel_ms, 3)})
+    return out
 
 
 def main():
@@ -319,7 +347,8 @@ def main():
     del probs
     if not args.no_extras:
         legs = {}
-        for name, fn in (("queens8", leg_queens8), ("rb_count", leg_rb), ("global", leg_global)):
+        for name, fn in (("queens8", leg_queens8), ("rb_count", leg_rb), ("global", leg_global),
+                         ("linear_ad", leg_linear_ad)):
             say(f"leg {name}")
             t = time.perf_counter()
             legs[name] = fn(ctx, cb, cspgen)
