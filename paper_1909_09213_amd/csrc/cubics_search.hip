@@ -234,11 +234,25 @@ DEV Unit ld_unit(const Unit *p, uint32_t i) {
 template <int WM>
 constexpr int row_batch() { return WM <= 2 ? 8 : (WM == 4 ? 4 : 2); }
 
+// Word k of row j - 1 of a row block, j >= 0: rm points at the block's row
+// -1 (the zero words before it), stride is the row length in bytes.  One
+// unsigned 32 x 32 + 64-bit multiply-add gives a row's address; the words of
+// a row then differ only by an immediate offset.
+template <bool GM>
+DEV uint32_t ld_row(const uint32_t *rm, uint32_t j, uint32_t stride, int k) {
+    const char *a = (const char *)rm + (unsigned long long)j * stride;
+    if constexpr (GM) return ((const __attribute__((address_space(1))) uint32_t *)a)[k];
+    else return ((const uint32_t *)a)[k];
+}
+
+// The next row_batch live values of word w of a domain, as value index + 1
+// (0 once the word is exhausted: row -1, the zero row).
 template <int WM>
-DEV void next_values(uint32_t &bits, int w, int (&ix)[row_batch<WM>()]) {
+DEV void next_values(uint32_t &bits, int w, uint32_t (&j)[row_batch<WM>()]) {
 #pragma unroll
     for (int q = 0; q < row_batch<WM>(); ++q) {
-        ix[q] = bits ? 32 * w + __ffs(bits) - 1 : -1;
+        const uint32_t lo = (uint32_t)(__ffs(bits));  // 1-based, 0 when empty
+        j[q] = w == 0 ? lo : (bits ? 32u * (uint32_t)w + lo : 0u);
         bits &= bits - 1u;
     }
 }
@@ -249,9 +263,7 @@ DEV void next_values(uint32_t &bits, int w, int (&ix)[row_batch<WM>()]) {
 // as soon as the union covers every target value, when the rest of the rows
 // cannot remove anything - else one row per live target value (bits over
 // the source), tested against the source domain.  *rows_read receives the
-// rows read (the algorithmic row traffic).  Rows are addressed as 32-bit
-// word offsets from the instance's row section (a uniform base), so that a
-// load needs one address instruction.
+// rows read (the algorithmic row traffic).
 template <int WM, bool GM>
 DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                      const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W, int *rows_read) {
@@ -262,12 +274,12 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
     *rows_read = 0;
     if (ty == U_TABLE) {
         const int ps = pop_w(ds, W), pt = pop_w(dt, W);
-        const uint32_t Wu = (uint32_t)W;
         if (ps <= pt) {
             uint32_t acc[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) acc[k] = 0u;
-            const uint32_t base = (uint32_t)u.p1;
+            const uint32_t *rm = I.rows + (uint32_t)u.p1 - W;  // row -1
+            const uint32_t stride = 4u * (uint32_t)W;
             int nread = 0;
             bool covered = false;
 #pragma unroll
@@ -275,14 +287,14 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                 if (w >= W || covered) break;
                 uint32_t bits = ds[w];
                 while (bits) {
-                    int ix[RB];
+                    uint32_t ix[RB];
                     next_values<WM>(bits, w, ix);
                     uint32_t r[RB][WM];
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
                         for (int k = 0; k < WM; ++k)
-                            r[q][k] = k < W ? ldg<GM>(I.rows, base + (uint32_t)ix[q] * Wu + (uint32_t)k) : 0u;
+                            r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
@@ -305,27 +317,28 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
             uint32_t keep[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) keep[k] = 0u;
-            const uint32_t base = (uint32_t)u.p0;
+            const uint32_t *rm = I.rows + (uint32_t)u.p0 - W;  // row -1
+            const uint32_t stride = 4u * (uint32_t)W;
 #pragma unroll
             for (int w = 0; w < WM; ++w) {
                 if (w >= W) break;
                 uint32_t bits = dt[w];
                 while (bits) {
-                    int ix[RB];
+                    uint32_t ix[RB];
                     next_values<WM>(bits, w, ix);
                     uint32_t r[RB][WM];
 #pragma unroll
                     for (int q = 0; q < RB; ++q)
 #pragma unroll
                         for (int k = 0; k < WM; ++k)
-                            r[q][k] = k < W ? ldg<GM>(I.rows, base + (uint32_t)ix[q] * Wu + (uint32_t)k) : 0u;
+                            r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
 #pragma unroll
                     for (int q = 0; q < RB; ++q) {
                         uint32_t hit = 0u;
 #pragma unroll
                         for (int k = 0; k < WM; ++k) hit |= r[q][k] & ds[k];
-                        // ix = -1 reads a zero row: never supported
-                        if (hit) keep[w] |= 1u << (ix[q] & 31);
+                        // ix = 0 reads the zero row: never supported
+                        if (hit) keep[w] |= 1u << ((ix[q] - 1u) & 31u);
                     }
                 }
             }
@@ -2455,11 +2468,17 @@ DEV InstDev rebase(const InstDev &g, const uint32_t *tab) {
     return I;
 }
 
+// Waves per SIMD the compiler must leave room for (domains of at most two
+// words); it bounds the registers per lane at 512 / CUBICS_LB_WAVES.
+#ifndef CUBICS_LB_WAVES
+#define CUBICS_LB_WAVES 4
+#endif
+
 // Persistent search kernel: every wavefront is a worker that pops tasks from
 // the global queue until no task is pending anywhere.  TL: a single-instance
 // solve whose packed tables are staged once per workgroup in LDS.
 template <int WM, bool TL, int FEAT, bool GLOB, bool SEGC, bool VAR = false>
-__global__ __launch_bounds__(512, WM <= 2 ? 4 : 1) void search_kernel(SearchParams P) {
+__global__ __launch_bounds__(512, WM <= 2 ? CUBICS_LB_WAVES : 1) void search_kernel(SearchParams P) {
     extern __shared__ uint32_t lds_raw[];
     // idle_token: 1 while one idle wave of this workgroup polls the global
     // queue; drained: set once that wave saw no task pending anywhere
