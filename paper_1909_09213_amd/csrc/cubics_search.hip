@@ -226,13 +226,20 @@ DEV Unit ld_unit(const Unit *p, uint32_t i) {
 }
 
 // Rows fetched together by one lane of a LANE table revision: the lane
-// gathers up to RB live values, then issues all their row loads before it
-// uses any, so a revision waits on ceil(|D| / RB) memory round trips instead
-// of |D|.  RB * WM <= 16 words are in flight per lane (wider rows, fewer of
-// them).  A missing value reads row -1, the W zero words the packer puts
-// before every row block.
+// gathers up to R live values, then issues all their row loads before it
+// uses any, so a revision waits on one memory round trip per batch instead
+// of one per row.  Most revisions end within a few rows (the union covers
+// the target early), and every slot of a batch costs the whole wave its
+// instructions whether or not the lane has a value for it, so batches are
+// short: 3 rows for domains of at most two words (measured against 1, 2, 4,
+// 6 and 8 on the 4096-instance batch, and against a short first batch
+// followed by longer ones).  A missing value reads row -1, the W zero words
+// the packer puts before every row block.
+#ifndef CUBICS_RB_NARROW
+#define CUBICS_RB_NARROW 3
+#endif
 template <int WM>
-constexpr int row_batch() { return WM <= 2 ? 8 : (WM == 4 ? 4 : 2); }
+constexpr int row_batch() { return WM <= 2 ? CUBICS_RB_NARROW : (WM == 4 ? 4 : 2); }
 
 // Word k of row j - 1 of a row block, j >= 0: rm points at the block's row
 // -1 (the zero words before it), stride is the row length in bytes.  One
@@ -245,15 +252,54 @@ DEV uint32_t ld_row(const uint32_t *rm, uint32_t j, uint32_t stride, int k) {
     else return ((const uint32_t *)a)[k];
 }
 
-// The next row_batch live values of word w of a domain, as value index + 1
-// (0 once the word is exhausted: row -1, the zero row).
-template <int WM>
-DEV void next_values(uint32_t &bits, int w, uint32_t (&j)[row_batch<WM>()]) {
+// The next R live values of word w of a domain, as value index + 1 (0 once
+// the word is exhausted: row -1, the zero row).
+template <int R>
+DEV void next_values(uint32_t &bits, int w, uint32_t (&j)[R]) {
 #pragma unroll
-    for (int q = 0; q < row_batch<WM>(); ++q) {
+    for (int q = 0; q < R; ++q) {
         const uint32_t lo = (uint32_t)(__ffs(bits));  // 1-based, 0 when empty
         j[q] = w == 0 ? lo : (bits ? 32u * (uint32_t)w + lo : 0u);
         bits &= bits - 1u;
+    }
+}
+
+// One batch of the union orientation: OR the rows of the next R source
+// values into acc.
+template <int R, int WM, bool GM>
+DEV void union_batch(const uint32_t *rm, uint32_t stride, uint32_t &bits, int w, int W, uint32_t (&acc)[WM]) {
+    uint32_t ix[R];
+    next_values<R>(bits, w, ix);
+    uint32_t r[R][WM];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < WM; ++k) acc[k] |= r[q][k];
+}
+
+// One batch of the test orientation: keep each of the next R target values
+// of word w whose row meets the source domain.
+template <int R, int WM, bool GM>
+DEV void test_batch(const uint32_t *rm, uint32_t stride, uint32_t &bits, int w, int W, const uint32_t (&ds)[WM],
+                    uint32_t &keep) {
+    uint32_t ix[R];
+    next_values<R>(bits, w, ix);
+    uint32_t r[R][WM];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int k = 0; k < WM; ++k) r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        uint32_t hit = 0u;
+#pragma unroll
+        for (int k = 0; k < WM; ++k) hit |= r[q][k] & ds[k];
+        // ix = 0 reads the zero row: never supported
+        if (hit) keep |= 1u << ((ix[q] - 1u) & 31u);
     }
 }
 
@@ -274,12 +320,12 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
     *rows_read = 0;
     if (ty == U_TABLE) {
         const int ps = pop_w(ds, W), pt = pop_w(dt, W);
+        const uint32_t stride = 4u * (uint32_t)W;
         if (ps <= pt) {
             uint32_t acc[WM];
 #pragma unroll
             for (int k = 0; k < WM; ++k) acc[k] = 0u;
             const uint32_t *rm = I.rows + (uint32_t)u.p1 - W;  // row -1
-            const uint32_t stride = 4u * (uint32_t)W;
             int nread = 0;
             bool covered = false;
 #pragma unroll
@@ -287,18 +333,7 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                 if (w >= W || covered) break;
                 uint32_t bits = ds[w];
                 while (bits) {
-                    uint32_t ix[RB];
-                    next_values<WM>(bits, w, ix);
-                    uint32_t r[RB][WM];
-#pragma unroll
-                    for (int q = 0; q < RB; ++q)
-#pragma unroll
-                        for (int k = 0; k < WM; ++k)
-                            r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
-#pragma unroll
-                    for (int q = 0; q < RB; ++q)
-#pragma unroll
-                        for (int k = 0; k < WM; ++k) acc[k] |= r[q][k];
+                    union_batch<RB, WM, GM>(rm, stride, bits, w, W, acc);
                     nread += RB;
                     uint32_t open = 0u;
 #pragma unroll
@@ -318,29 +353,11 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
 #pragma unroll
             for (int k = 0; k < WM; ++k) keep[k] = 0u;
             const uint32_t *rm = I.rows + (uint32_t)u.p0 - W;  // row -1
-            const uint32_t stride = 4u * (uint32_t)W;
 #pragma unroll
             for (int w = 0; w < WM; ++w) {
                 if (w >= W) break;
                 uint32_t bits = dt[w];
-                while (bits) {
-                    uint32_t ix[RB];
-                    next_values<WM>(bits, w, ix);
-                    uint32_t r[RB][WM];
-#pragma unroll
-                    for (int q = 0; q < RB; ++q)
-#pragma unroll
-                        for (int k = 0; k < WM; ++k)
-                            r[q][k] = k < W ? ld_row<GM>(rm, ix[q], stride, k) : 0u;
-#pragma unroll
-                    for (int q = 0; q < RB; ++q) {
-                        uint32_t hit = 0u;
-#pragma unroll
-                        for (int k = 0; k < WM; ++k) hit |= r[q][k] & ds[k];
-                        // ix = 0 reads the zero row: never supported
-                        if (hit) keep[w] |= 1u << ((ix[q] - 1u) & 31u);
-                    }
-                }
+                while (bits) test_batch<RB, WM, GM>(rm, stride, bits, w, W, ds, keep[w]);
             }
 #pragma unroll
             for (int k = 0; k < WM; ++k) nw[k] = keep[k];
