@@ -24,7 +24,9 @@
  *    reasoning for sum a_t x_t <= b with positive a_t; unary constraints
  *    restrict the root domains; the all-different of type 7 is propagated
  *    to generalized arc consistency instead (the stronger propagation the
- *    paper names as future work, Sec. 3);
+ *    paper names as future work, Sec. 3), and the linear <= of type 8 is
+ *    bounded together with the all-different constraints inside its scope
+ *    (revise_linear_ad);
  *  - a node is every propagation call: the root and every child tried,
  *    failed children included;
  *  - a table constraint is given over the original domains and is
@@ -34,7 +36,7 @@
  *
  * Parity status: every function in this file is pinned by the CPU tests
  * (brute force, the paper's worked example, n-queens counts, closed forms,
- * tree-CSP counts); none is "parity unpinned".
+ * tree-CSP counts, definition-level searches); none is "parity unpinned".
  */
 #include <stdint.h>
 #include <stdlib.h>
