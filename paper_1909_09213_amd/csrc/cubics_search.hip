@@ -303,13 +303,17 @@ DEV void test_batch(const uint32_t *rm, uint32_t stride, uint32_t &bits, int w, 
     }
 }
 
-// LANE layout: full new target words for one unit.  A table revision reads
-// at most min(|D_src|, |D_tgt|) rows: the union of the source values' rows
-// (bits over the target) when the source is the smaller domain - stopping
-// as soon as the union covers every target value, when the rest of the rows
-// cannot remove anything - else one row per live target value (bits over
-// the source), tested against the source domain.  *rows_read receives the
-// rows read (the algorithmic row traffic).
+// LANE layout: full new target words for one unit.  A table revision first
+// ORs the rows of up to RB source values (bits over the target: the values
+// of the source's lowest non-empty word); a target value that union covers
+// is supported.  If those were all the source's values, the union is exact.
+// Otherwise each target value still open has its own row (bits over the
+// source) tested against the source domain.  With at most RB target values
+// the revision tests them all at once instead.  So a revision reads at most
+// RB + (open target values) rows, and most end after one batch: a lane's
+// batch costs its wave every slot, so no lane walks a long union for the
+// one value it removes.  *rows_read receives the rows read (the algorithmic
+// row traffic).
 template <int WM, bool GM>
 DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
                      const uint32_t (&dt)[WM], uint32_t (&nw)[WM], int W, int *rows_read) {
@@ -321,47 +325,35 @@ DEV void revise_lane(const InstDev &I, const Unit &u, const uint32_t (&ds)[WM],
     if (ty == U_TABLE) {
         const int ps = pop_w(ds, W), pt = pop_w(dt, W);
         const uint32_t stride = 4u * (uint32_t)W;
-        if (ps <= pt) {
-            uint32_t acc[WM];
+        const uint32_t *rs = I.rows + (uint32_t)u.p1 - W;  // row -1, rows by source value
+        const uint32_t *rt = I.rows + (uint32_t)u.p0 - W;  // row -1, rows by target value
+        uint32_t acc[WM], keep[WM], open[WM];
 #pragma unroll
-            for (int k = 0; k < WM; ++k) acc[k] = 0u;
-            const uint32_t *rm = I.rows + (uint32_t)u.p1 - W;  // row -1
-            int nread = 0;
-            bool covered = false;
+        for (int k = 0; k < WM; ++k) acc[k] = keep[k] = 0u;
+        // the source's lowest non-empty word
+        int w0 = 0;
+        uint32_t b0 = 0u;
 #pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (w >= W || covered) break;
-                uint32_t bits = ds[w];
-                while (bits) {
-                    union_batch<RB, WM, GM>(rm, stride, bits, w, W, acc);
-                    nread += RB;
-                    uint32_t open = 0u;
+        for (int k = WM - 1; k >= 0; --k)
+            if (k < W && ds[k]) w0 = k;
 #pragma unroll
-                    for (int k = 0; k < WM; ++k) open |= dt[k] & ~acc[k];
-                    if (open == 0u) {
-                        covered = true;
-                        break;
-                    }
-                }
-            }
-            *rows_read = min(nread, ps);
+        for (int k = 0; k < WM; ++k) b0 = (k == w0) ? ds[k] : b0;
+        const int n0 = __popc(b0);
+        const bool direct = pt <= RB;
+        uint32_t ub = direct ? 0u : b0;
+        if (ub) union_batch<RB, WM, GM>(rs, stride, ub, w0, W, acc);
+        const bool exact = !direct && ub == 0u && n0 == ps;
 #pragma unroll
-            for (int k = 0; k < WM; ++k) nw[k] = dt[k] & acc[k];
-        } else {
-            *rows_read = pt;
-            uint32_t keep[WM];
+        for (int k = 0; k < WM; ++k) open[k] = exact ? 0u : (dt[k] & ~acc[k]);
+        *rows_read = (direct ? 0 : min(n0, RB)) + pop_w(open, W);
 #pragma unroll
-            for (int k = 0; k < WM; ++k) keep[k] = 0u;
-            const uint32_t *rm = I.rows + (uint32_t)u.p0 - W;  // row -1
-#pragma unroll
-            for (int w = 0; w < WM; ++w) {
-                if (w >= W) break;
-                uint32_t bits = dt[w];
-                while (bits) test_batch<RB, WM, GM>(rm, stride, bits, w, W, ds, keep[w]);
-            }
-#pragma unroll
-            for (int k = 0; k < WM; ++k) nw[k] = keep[k];
+        for (int w = 0; w < WM; ++w) {
+            if (w >= W) break;
+            uint32_t bits = open[w];
+            while (bits) test_batch<RB, WM, GM>(rt, stride, bits, w, W, ds, keep[w]);
         }
+#pragma unroll
+        for (int k = 0; k < WM; ++k) nw[k] = (dt[k] & acc[k]) | keep[k];
     } else if (ty == U_NEQ) {
         if (pop_w(ds, W) == 1) {
             int a = low_w(ds, W) + u.p0;
